@@ -1,0 +1,59 @@
+"""Pins of the element matrices through plane-wave analysis of the assembled operator."""
+import numpy as np
+import pytest
+
+from oracle import dispersion as dsp
+from oracle import element as el
+
+RHO, VS, VP = 2000.0, 1000.0, 2000.0
+MU = RHO * VS ** 2
+LAM = RHO * VP ** 2 - 2 * MU
+
+
+def _ovfem(h=1.0):
+    Kl, Km = el.ovfem_reference()
+    return h * (LAM * Kl + MU * Km)
+
+
+@pytest.mark.parametrize("kh", [0.2, 2 * np.pi / 10, 2 * np.pi / 5, 2.0])
+@pytest.mark.parametrize("which", ["ovfem", "trilinear"])
+def test_axis_aligned_waves_follow_the_1d_closed_form(kh, which):
+    """Along a grid axis both elements reduce to the 1D lattice: c_h / c = sin(kh/2) / (kh/2)."""
+    h = 1.0
+    K = _ovfem(h) if which == "ovfem" else el.trilinear_stiffness(LAM, MU, h)
+    c = dsp.phase_velocities(K, RHO, h, (0, 0, 1), kh)
+    ratio = np.sin(kh / 2) / (kh / 2)
+    assert np.allclose(c, [VS * ratio, VS * ratio, VP * ratio], rtol=1e-12)
+
+
+@pytest.mark.parametrize("direction", [(1, 1, 1), (1, 2, 3), (1, 1, 0)])
+def test_second_order_convergence_of_phase_velocity(direction):
+    h = 1.0
+    K = _ovfem(h)
+    errs = []
+    for kh in (0.2, 0.1):
+        c = dsp.phase_velocities(K, RHO, h, direction, kh)
+        errs.append(np.abs(c / np.array([VS, VS, VP]) - 1.0))
+    ratio = errs[0] / errs[1]
+    assert np.all((ratio > 3.9) & (ratio < 4.1)), ratio
+
+
+@pytest.mark.parametrize("ppw", [10, 5])
+def test_ovfem_less_dispersive_than_trilinear_off_axis(ppw):
+    """OVFEM suppresses the dispersion of the lumped trilinear element (Sec. 2, Sec. 3 Table 2)."""
+    h, kh = 1.0, 2 * np.pi / ppw
+    ref = np.array([VS, VS, VP])
+    eo = np.abs(dsp.phase_velocities(_ovfem(h), RHO, h, (1, 1, 1), kh) / ref - 1)
+    et = np.abs(dsp.phase_velocities(el.trilinear_stiffness(LAM, MU, h), RHO, h, (1, 1, 1), kh) / ref - 1)
+    assert np.all(eo < et)
+    # P wave also along a face diagonal
+    eo2 = abs(dsp.phase_velocities(_ovfem(h), RHO, h, (1, 1, 0), kh)[2] / VP - 1)
+    et2 = abs(dsp.phase_velocities(el.trilinear_stiffness(LAM, MU, h), RHO, h, (1, 1, 0), kh)[2] / VP - 1)
+    assert eo2 < et2
+
+
+def test_highest_lattice_frequency_gives_cfl_h_over_vp():
+    """omega_max = 2 Vp / h on the lattice (Vp = 2 Vs), so central differences need dt < h / Vp."""
+    h = 1.0
+    w = dsp.max_frequency(_ovfem(h), RHO, h, n=8)
+    assert w == pytest.approx(2 * VP / h, rel=1e-12)

@@ -1,0 +1,117 @@
+"""Pins of the oracle's time stepper: energy, reciprocity, stability, finite speed, adjoint."""
+import numpy as np
+import pytest
+
+from oracle import assembly as asm
+from paper_2404_13683_amd import workloads as wl
+
+
+def _hetero_model(nx=6, ny=5, nz=5, h=2.0, seed=0, cfl=0.5):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(1800, 2500, (nz, ny, nx))
+    vs = rng.uniform(600, 1200, (nz, ny, nx))
+    lam, mu = wl.lame_from_velocities(2 * vs, vs, rho)
+    dt = wl.stable_dt(h, lam, mu, rho, cfl)
+    fixed = wl.box_fixed(nx, ny, nz)
+    return asm.Model(lam, mu, rho, h, fixed, dt), dt
+
+
+def test_unforced_energy_is_conserved():
+    m, dt = _hetero_model()
+    rng = np.random.default_rng(1)
+    u0 = rng.standard_normal(m.node_shape) * m.free[..., None]
+    up = u0.copy()
+    nt = 300
+    zero = np.zeros((1, nt))
+    tr, u, uprev, states = asm.simulate(m, nt, [0], [0], zero, [0], u0=u0, u_prev=up, keep_states=True)
+    e = [asm.energy(m, states[n + 1], states[n]) for n in range(nt)]
+    e = np.array(e)
+    assert e[0] > 0
+    assert np.abs(e - e[0]).max() <= 1e-12 * e[0]
+
+
+def test_source_receiver_reciprocity():
+    """trace_B,j(force at A,i) == trace_A,i(force at B,j): (M^-1 K)^k M^-1 is symmetric."""
+    m, dt = _hetero_model(nx=7, ny=6, nz=5, seed=2)
+    nx, ny, nz = m.nx, m.ny, m.nz
+    A = wl.node_id(2, 2, nz, nx, ny)
+    B = wl.node_id(5, 3, 2, nx, ny)
+    nt = 120
+    w = wl.ricker(nt, dt, 1.0 / (30 * dt))[None, :]
+    tA, *_ = asm.simulate(m, nt, [A], [0], w, [B])   # x-force at A, record at B
+    tB, *_ = asm.simulate(m, nt, [B], [2], w, [A])   # z-force at B, record at A
+    s1 = tA[0, 2]   # z at B
+    s2 = tB[0, 0]   # x at A
+    assert np.abs(s1).max() > 0
+    assert np.abs(s1 - s2).max() <= 1e-11 * np.abs(s1).max()
+
+
+@pytest.mark.parametrize("cfl,all_fixed,grows", [
+    (0.5, True, False), (0.95, True, False), (1.15, True, True),
+    # free faces: corner nodes carry rho h^3 / 8, so the element bound
+    # 2 / omega_max(K_e, rho h^3 / 8) = h / (sqrt(2) Vp) governs instead
+    (0.69, False, False), (0.95, False, True)])
+def test_stability_limit(cfl, all_fixed, grows):
+    nx = ny = nz = 10
+    h = 1.0
+    rho = np.full((nz, ny, nx), 2000.0)
+    lam, mu = wl.lame_from_velocities(np.full_like(rho, 2000.0), np.full_like(rho, 1000.0), rho)
+    dt = cfl * h / 2000.0
+    fixed = np.zeros((nz + 1, ny + 1, nx + 1), np.uint8)
+    if all_fixed:
+        fixed[0] = fixed[-1] = 1
+        fixed[:, 0] = fixed[:, -1] = 1
+        fixed[:, :, 0] = fixed[:, :, -1] = 1
+    m = asm.Model(lam, mu, rho, h, fixed, dt)
+    rng = np.random.default_rng(3)
+    u0 = rng.standard_normal(m.node_shape)
+    zero = np.zeros((1, 400))
+    _, u, _, _ = asm.simulate(m, 400, [0], [0], zero, [0], u0=u0, u_prev=u0)
+    amp = np.abs(u).max() / np.abs(u0).max()
+    assert (amp > 1e3) == grows
+
+
+def test_finite_propagation_speed_one_node_per_step():
+    """K couples only nearest nodes, so after n steps a point force reaches n nodes away."""
+    m, dt = _hetero_model(nx=12, ny=12, nz=12, seed=4)
+    src = wl.node_id(6, 6, 6, 12, 12)
+    nt = 4
+    w = np.ones((1, nt))
+    _, u, _, _ = asm.simulate(m, nt, [src], [1], w, [0])
+    nz_idx = np.argwhere(np.abs(u).sum(-1) > 0)
+    d = np.abs(nz_idx - np.array([6, 6, 6])).max()
+    assert d == nt - 1   # u^{n} is nonzero up to n-1 nodes away (F^0 enters u^1 locally)
+
+
+def test_adjoint_gradient_matches_central_differences():
+    m, dt = _hetero_model(nx=5, ny=4, nz=4, seed=5)
+    nx, ny, nz = m.nx, m.ny, m.nz
+    nt = 60
+    src = [wl.node_id(2, 2, nz, nx, ny)]
+    rec = [wl.node_id(1, 1, nz, nx, ny), wl.node_id(3, 2, nz, nx, ny), wl.node_id(2, 1, 2, nx, ny)]
+    w = wl.ricker(nt, dt, 1.0 / (20 * dt))[None, :]
+    # synthetic observations from a perturbed model
+    rng = np.random.default_rng(6)
+    mt = asm.Model(m.lam * (1 + 0.1 * rng.standard_normal(m.lam.shape)), m.mu, m.rho, m.h,
+                   wl.box_fixed(nx, ny, nz), dt)
+    d_obs, *_ = asm.simulate(mt, nt, src, [2], w, rec)
+    J, gl, gm = asm.adjoint_gradient(m, nt, src, [2], w, rec, d_obs)
+    J2, gl2, gm2 = asm.adjoint_gradient(m, nt, src, [2], w, rec, d_obs, ckpt_every=7)
+    assert J == J2 and np.array_equal(gl, gl2) and np.array_equal(gm, gm2)
+
+    def J_of(lam, mu):
+        mm = asm.Model(lam, mu, m.rho, m.h, wl.box_fixed(nx, ny, nz), dt)
+        tr, *_ = asm.simulate(mm, nt, src, [2], w, rec)
+        return asm.misfit(tr, d_obs)
+
+    for (k, j, i) in [(3, 2, 2), (2, 1, 1), (0, 0, 4), (3, 0, 1)]:
+        for which, g in (("lam", gl), ("mu", gm)):
+            lam, mu = m.lam.copy(), m.mu.copy()
+            base = (lam if which == "lam" else mu)[k, j, i]
+            eps = 1e-4 * base
+            (lam if which == "lam" else mu)[k, j, i] = base + eps
+            jp = J_of(lam, mu)
+            (lam if which == "lam" else mu)[k, j, i] = base - eps
+            jm = J_of(lam, mu)
+            fd = (jp - jm) / (2 * eps)
+            assert g[k, j, i] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(g).max())
