@@ -1,0 +1,156 @@
+"""Benchmark of the fused OVFEM stepper on one MI355X.
+
+Workload (one step = one pass of the whole hot path: gather, element products,
+assembly and the central-difference update, with source injection and receivers):
+three horizontal layers on 256 x 256 x 128 voxels (8.4 M elements, ~25 M free
+DOF), h = 5 m, Vs 300/800/2000 m/s, Vp = 2 Vs, rho 1800/2100/2500 kg/m^3, seeded
++-10 % Gaussian-correlated (L = 50 m) lam/mu perturbation, Ricker 5 Hz, dt at
+0.5 x CFL.  Inputs are synthetic and already resident in HBM when timing starts.
+
+Both element-product paths run from reset for warmup + steps time steps: the
+plain FP64 path and the INT8 matrix-core path.  `value` is the INT8 path's
+DOF-updates per second; the FP64 path, their ratio and the INT8-vs-FP64 receiver
+trace error are reported beside it.  The CPU oracle is timed on a bounded sample
+of the same workload on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s/step: INT8-MFMA vs FP64 path at ≤1e-9 trace rel err; % roofline"
+HBM_PEAK = 8.0e12          # bytes/s
+INT8_PEAK = 5.0e15         # dense INT8 MFMA ops/s
+FP64_PEAK = 78.6e12        # FP64 vector flop/s
+INT8_OPS_PER_ELEMENT = 2 * 48 * 24 * 8    # [AL; AM] (48 x 24) times 8 digit slices
+FP64_FLOP_PER_ELEMENT = 2 * 2 * 24 * 24   # AL u and AM u in FP64
+
+
+def algorithmic_bytes(nx, ny, nz):
+    """Bytes a step must move: u^n, u^{n-1} read, u^{n+1} written, dt^2/m per node; lam, mu per element."""
+    nodes = (nx + 1) * (ny + 1) * (nz + 1)
+    return 80 * nodes + 16 * nx * ny * nz
+
+
+def time_path(wl, prec, warmup, steps):
+    import torch
+
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver.from_workload(wl, precision=prec, receivers_nt=warmup + steps)
+    s.reset()
+    s.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(steps, 1)
+    traces = s.get_traces().cpu().numpy()
+    s.close()
+    return ms, traces
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The oracle stepping the same model on the host: whole steps until the budget is spent."""
+    from oracle import assembly as oasm
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    m = oasm.Model(wl.lam, wl.mu, wl.rho, wl.h, wl.fixed, wl.dt)
+    u = np.zeros(m.node_shape)
+    up = np.zeros(m.node_shape)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        F = oasm.forcing(m.node_shape, wl.src_node, wl.src_comp, wl.wavelet[:, n])
+        un = m.step(u, up, F)
+        up, u = u, un
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": wl.free_dof() * n / dt, "unit": "DOF-updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d full steps of the same 256x256x128 workload (numpy FP64 oracle, %.1f s)" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--paths", default="fp64,int8")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
+              "sharding is described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_13683_amd import workloads
+
+    torch.cuda.set_device(0)
+    wl = workloads.layered_c2(nt=args.warmup + args.steps)
+    free_dof = wl.free_dof()
+    paths = args.paths.split(",")
+    res = {}
+    for p in paths:
+        ms, tr = time_path(wl, p, args.warmup, args.steps)
+        res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "traces": tr}
+        print("[bench] %s: %.4f ms/step, %.4e DOF-updates/s" % (p, ms, res[p]["value"]), file=sys.stderr, flush=True)
+    head = "int8" if "int8" in res else paths[0]
+    ms = res[head]["ms_per_step"]
+    n_elem = wl.nx * wl.ny * wl.nz
+    bytes_step = algorithmic_bytes(wl.nx, wl.ny, wl.nz)
+    hbm = bytes_step / (ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": res[head]["value"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8-mfma+f64" if head == "int8" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "layered-256x256x128 (8.4M voxels, %d free DOF), h=5 m, Ricker 5 Hz, dt=%.4e s"
+                               % (free_dof, wl.dt),
+                   "path": head, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz},
+        "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": hbm / HBM_PEAK, "traffic": None,
+                     "algorithmic_bytes_per_step": bytes_step,
+                     "mfma_frac": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / INT8_PEAK if head == "int8" else None},
+    }
+    if "fp64" in res:
+        f = res["fp64"]
+        out["fp64_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"],
+                            "fp64_frac": FP64_FLOP_PER_ELEMENT * n_elem / (f["ms_per_step"] * 1e-3) / FP64_PEAK,
+                            "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK}
+    if "fp64" in res and "int8" in res:
+        a, b = res["int8"]["traces"], res["fp64"]["traces"]
+        out["int8_vs_fp64"] = {"speedup": res["fp64"]["ms_per_step"] / res["int8"]["ms_per_step"],
+                               "trace_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                               "steps_compared": args.warmup + args.steps}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * ovfem.h -- C ABI of libovfem, an MI355X (gfx950) explicit elastic-wave stepper on
+ * the low-ordered orthogonal voxel finite element (OVFEM) of arXiv 2404.13683.
+ *
+ * What the library computes (all citations are to that paper):
+ *   - the element-by-element stiffness product f = K u over cubic voxel elements,
+ *     K_e = h (lam_e K_lam + mu_e K_mu), where K_lam, K_mu are the fixed reference
+ *     matrices of the OVFEM element (Sec. 2, Eq. (5) with the Heaviside displacement
+ *     basis of Eq. (7) and the stress basis of Eq. (8)); 256 K_lam and 128 K_mu are
+ *     integer matrices with entries inside the INT8 range;
+ *   - fused with the central-difference update with the exactly diagonal OVFEM mass
+ *     (Sec. 2, Eqs. (3) and (6)):
+ *         u^{n+1} = 2 u^n - u^{n-1} + dt^2 M^{-1} (F^n - K u^n),
+ *     fixed DOFs held at zero;
+ *   - in two precisions: OVFEM_FP64 evaluates the element products in FP64; OVFEM_INT8
+ *     splits u into INT8 digit slices under a per-tile power-of-two exponent, runs the
+ *     products on INT8 matrix cores with INT32 accumulation and recombines the slices
+ *     exactly into FP64 (Sec. 2, Eqs. (10)-(17), hierarchical FP64-INT64-INT8 form);
+ *     everything outside the INT8 products is FP64 (Sec. 3).
+ *
+ * Grid layout (shared by every array argument):
+ *   elements e = i + nx (j + ny k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
+ *   nodes    n = i + (nx+1) (j + (ny+1) k), 0 <= i <= nx, ...;  z points up;
+ *   element e spans nodes i..i+1, j..j+1, k..k+1; voxel edge h.
+ *   Nodal vectors are [node][3] float64 (x, y, z components interleaved).
+ *
+ * Pointers: arguments documented as HOST are ordinary CPU memory; arguments
+ * documented as DEVICE are GPU memory on the solver's device (for example the
+ * data_ptr() of a torch tensor).  Uploads copy: the caller keeps ownership of every
+ * buffer it passes and may free it when the call returns.  The solver owns all of its
+ * device state.  All GPU work is enqueued on the stream given at creation; calls that
+ * return data to the host, and ovfem_synchronize, wait for that stream.
+ *
+ * Errors: every call returns an ovfem_status (0 = success, negative = failure) and
+ * never throws.  On failure the call has no effect on the solver, and
+ * ovfem_last_error() returns a message for the calling thread.
+ */
+#ifndef OVFEM_H
+#define OVFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ovfem_status;
+#define OVFEM_OK 0
+#define OVFEM_EINVAL (-1)  /* invalid argument: size, index, range, null pointer */
+#define OVFEM_ENOMEM (-2)  /* device or host allocation failed */
+#define OVFEM_EDEVICE (-3) /* HIP runtime or kernel launch error */
+#define OVFEM_ESTATE (-4)  /* call not valid in the solver's current state */
+
+/* precision of the element products */
+#define OVFEM_FP64 0
+#define OVFEM_INT8 1
+
+typedef struct ovfem_solver ovfem_solver;
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t ovfem_version(void);
+
+/* Message describing the last failed call on this thread ("" if none).  The string
+ * stays valid until the next library call on the same thread. */
+const char* ovfem_last_error(void);
+
+/* Create a solver for an nx x ny x nz voxel grid of edge h (> 0) on the current HIP
+ * device.  n_shots must be 1.  precision is OVFEM_FP64 or OVFEM_INT8.  stream is a
+ * hipStream_t (NULL = the legacy default stream); all work is enqueued on it.
+ * EINVAL for non-positive sizes, h <= 0, unknown precision; ENOMEM if the device
+ * buffers do not fit. */
+ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz, double h,
+                          int32_t n_shots, int32_t precision, void* stream);
+
+/* Free every device buffer of the solver (waits for its stream).  NULL is accepted. */
+ovfem_status ovfem_destroy(ovfem_solver* s);
+
+/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8). */
+ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision);
+
+/* Per-element material, HOST arrays of nx*ny*nz float64: Lame lam, shear modulus mu,
+ * density rho; solid (nullable, uint8, 0 = removed voxel) marks voxels that are
+ * absent.  The nodal mass is the sum of rho h^3 / 8 over the solid voxels touching a
+ * node (Sec. 2, Eq. (6): the OVFEM mass is diagonal without approximation); nodes with
+ * no mass do not move.  EINVAL if mu <= 0, lam + 2 mu / 3 <= 0, rho <= 0 or a value is
+ * not finite in a solid voxel.  Resets the wavefield and traces. */
+ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* mu, const double* rho,
+                             const uint8_t* solid);
+
+/* Fixed nodes, HOST array of (nx+1)(ny+1)(nz+1) uint8 (nullable = none fixed); a
+ * nonzero entry holds all three DOFs of that node at zero. */
+ovfem_status ovfem_set_fixed_nodes(ovfem_solver* s, const uint8_t* fixed);
+
+/* Time step dt (> 0).  EINVAL if dt exceeds the element-wise stability bound
+ * 2 / sqrt(max eigenvalue of K_e / (rho_e h^3 / 8)) over solid voxels, which bounds
+ * the central-difference limit of the assembled system from below. */
+ovfem_status ovfem_set_dt(ovfem_solver* s, double dt);
+
+/* Point forces, HOST arrays: n sources at nodes node[i] (flat node id), component
+ * comp[i] in {0, 1, 2}, shot[i] (nullable = all 0; must be < n_shots), with force
+ * wavelet[i * nt + t] applied at step t (time t dt); no force after step nt - 1.
+ * n = 0 removes all sources.  EINVAL for out-of-range indices. */
+ovfem_status ovfem_set_sources(ovfem_solver* s, int32_t n, const int64_t* node, const int32_t* comp,
+                               const int32_t* shot, const double* wavelet, int64_t nt);
+
+/* Receivers, HOST array of n flat node ids (the same for every shot).  After step t
+ * (t < nt_max) the three components of u^{t+1} at each receiver are recorded.  Clears
+ * the recorded traces.  EINVAL for out-of-range ids or nt_max < 0. */
+ovfem_status ovfem_set_receivers(ovfem_solver* s, int32_t n, const int64_t* node, int64_t nt_max);
+
+/* u^0 = u^{-1} = 0, step counter 0, traces cleared. */
+ovfem_status ovfem_reset(ovfem_solver* s);
+
+/* Enqueue n >= 0 time steps on the solver's stream (asynchronous).  Requires the
+ * model and dt.  Step t uses the force at step t and records receivers into slot t
+ * while t < nt_max. */
+ovfem_status ovfem_step(ovfem_solver* s, int64_t n);
+
+/* f = K u for one nodal vector with the solver's current precision and model, no
+ * boundary conditions applied (rows of fixed nodes are included).  u and Ku are
+ * DEVICE arrays of (nx+1)(ny+1)(nz+1)*3 float64; they must not overlap.  The
+ * wavefield state of the solver is not touched.  Asynchronous on the stream. */
+ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku);
+
+/* Copy u^n (which = 0) or u^{n-1} (which = 1) into the DEVICE array out
+ * ((nx+1)(ny+1)(nz+1)*3 float64).  Waits for the stream. */
+ovfem_status ovfem_get_wavefield(ovfem_solver* s, int32_t which, double* out);
+
+/* Replace the state by (u^n = un, u^{n-1} = unm1) at step counter `step` (>= 0).
+ * DEVICE arrays as in ovfem_get_wavefield.  Resumes a run from a saved state. */
+ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double* unm1, int64_t step);
+
+/* Recorded traces into the DEVICE array out, float64 laid out
+ * [shot][receiver][component][t] with t < nt_max; slots of steps not yet run are 0.
+ * Waits for the stream. */
+ovfem_status ovfem_get_traces(ovfem_solver* s, double* out);
+
+/* Current step counter (number of steps taken since reset / set_wavefield). */
+ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step);
+
+/* Wait for all work enqueued by the solver. */
+ovfem_status ovfem_synchronize(ovfem_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OVFEM_H */

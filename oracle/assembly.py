@@ -264,3 +264,24 @@ def dense_stiffness(lam, mu, h):
                     for b, q in enumerate(dofs):
                         K[p, q] += Ke[a, b]
     return K
+
+
+def matvec_at_nodes(u, lam, mu, h, nodes):
+    """(K u) at the listed nodes only: each from its (up to 8) touching elements.
+
+    u is the full nodal array (nz+1, ny+1, nx+1, 3); nodes are (k, j, i) triples.
+    Used to check full-size results on a sample of outputs.
+    """
+    Kl, Km = ovfem_reference()
+    nz, ny, nx = lam.shape
+    out = np.zeros((len(nodes), 3))
+    for r, (k, j, i) in enumerate(nodes):
+        for alpha in range(8):  # the node is corner alpha of element (i-di, j-dj, k-dk)
+            di, dj, dk = alpha & 1, (alpha >> 1) & 1, (alpha >> 2) & 1
+            ei, ej, ek = i - di, j - dj, k - dk
+            if not (0 <= ei < nx and 0 <= ej < ny and 0 <= ek < nz):
+                continue
+            ue = np.concatenate([u[ek + ((b >> 2) & 1), ej + ((b >> 1) & 1), ei + (b & 1)] for b in range(8)])
+            ye = h * (lam[ek, ej, ei] * (Kl @ ue) + mu[ek, ej, ei] * (Km @ ue))
+            out[r] += ye[3 * alpha:3 * alpha + 3]
+    return out

@@ -1,0 +1,216 @@
+"""ctypes binding of libovfem (include/ovfem.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library.  Host-side inputs (model,
+fixed nodes, sources, receivers) are numpy arrays; nodal vectors that live on the GPU
+(matvec operands, wavefields, traces) are torch CUDA float64 tensors, used only for
+device memory and the stream.  If the library is missing this module raises on
+import: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libovfem.so")
+
+OVFEM_FP64 = 0
+OVFEM_INT8 = 1
+PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8}
+
+# name -> (restype, argtypes); mirrors include/ovfem.h
+_i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+SIGNATURES = {
+    "ovfem_version": (_i32, []),
+    "ovfem_last_error": (ctypes.c_char_p, []),
+    "ovfem_create": (_i32, [ctypes.POINTER(_vp), _i64, _i64, _i64, _f64, _i32, _i32, _vp]),
+    "ovfem_destroy": (_i32, [_vp]),
+    "ovfem_set_precision": (_i32, [_vp, _i32]),
+    "ovfem_set_model": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "ovfem_set_fixed_nodes": (_i32, [_vp, _vp]),
+    "ovfem_set_dt": (_i32, [_vp, _f64]),
+    "ovfem_set_sources": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i64]),
+    "ovfem_set_receivers": (_i32, [_vp, _i32, _vp, _i64]),
+    "ovfem_reset": (_i32, [_vp]),
+    "ovfem_step": (_i32, [_vp, _i64]),
+    "ovfem_matvec": (_i32, [_vp, _vp, _vp]),
+    "ovfem_get_wavefield": (_i32, [_vp, _i32, _vp]),
+    "ovfem_set_wavefield": (_i32, [_vp, _vp, _vp, _i64]),
+    "ovfem_get_traces": (_i32, [_vp, _vp]),
+    "ovfem_get_step": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "ovfem_synchronize": (_i32, [_vp]),
+}
+
+
+class OvfemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libovfem status %d: %s" % (status, msg))
+        self.status = status
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("libovfem.so not built at %s (run __graft_entry__.build())" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = load_library()
+
+
+def lib():
+    return _LIB
+
+
+def _check(status):
+    if status != 0:
+        raise OvfemError(status, _LIB.ovfem_last_error().decode())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_f64(t, n, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("%s must be a contiguous CUDA float64 tensor" % name)
+    if t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One OVFEM grid on the current GPU; all work on torch's current stream."""
+
+    def __init__(self, nx, ny, nz, h, precision="fp64", n_shots=1, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.nx, self.ny, self.nz, self.h = int(nx), int(ny), int(nz), float(h)
+        self.n_shots = int(n_shots)
+        self.n_nodes = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+        self._h = ctypes.c_void_p()
+        _check(_LIB.ovfem_create(ctypes.byref(self._h), self.nx, self.ny, self.nz, self.h, self.n_shots,
+                                 PRECISIONS[precision], ctypes.c_void_p(stream.cuda_stream)))
+        self.n_rec = 0
+        self.rec_nt = 0
+
+    def close(self):
+        if self._h:
+            _check(_LIB.ovfem_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- configuration (host arrays)
+    def set_precision(self, precision):
+        _check(_LIB.ovfem_set_precision(self._h, PRECISIONS[precision]))
+
+    def set_model(self, lam, mu, rho, solid=None):
+        la, lp = _host(lam, np.float64)
+        ma, mp = _host(mu, np.float64)
+        ra, rp = _host(rho, np.float64)
+        n = self.nx * self.ny * self.nz
+        for a in (la, ma, ra):
+            if a.size != n:
+                raise ValueError("material arrays must have nx*ny*nz entries")
+        sp = None
+        if solid is not None:
+            sa, sp = _host(solid, np.uint8)
+            if sa.size != n:
+                raise ValueError("solid must have nx*ny*nz entries")
+        _check(_LIB.ovfem_set_model(self._h, lp, mp, rp, sp))
+
+    def set_fixed_nodes(self, fixed):
+        if fixed is None:
+            _check(_LIB.ovfem_set_fixed_nodes(self._h, None))
+            return
+        fa, fp = _host(fixed, np.uint8)
+        if fa.size != self.n_nodes:
+            raise ValueError("fixed must have one entry per node")
+        _check(_LIB.ovfem_set_fixed_nodes(self._h, fp))
+
+    def set_dt(self, dt):
+        _check(_LIB.ovfem_set_dt(self._h, float(dt)))
+
+    def set_sources(self, node, comp, wavelet, shot=None):
+        na, np_ = _host(node, np.int64)
+        ca, cp = _host(comp, np.int32)
+        wa, wp = _host(wavelet, np.float64)
+        n = int(na.size)
+        nt = int(wa.shape[-1]) if n else 0
+        if n and wa.size != n * nt:
+            raise ValueError("wavelet must be (n_sources, nt)")
+        sp = None
+        if shot is not None:
+            sa, sp = _host(shot, np.int32)
+        _check(_LIB.ovfem_set_sources(self._h, n, np_, cp, sp, wp, nt))
+
+    def set_receivers(self, node, nt_max):
+        na, np_ = _host(node, np.int64)
+        _check(_LIB.ovfem_set_receivers(self._h, int(na.size), np_, int(nt_max)))
+        self.n_rec, self.rec_nt = int(na.size), int(nt_max)
+
+    @classmethod
+    def from_workload(cls, wl, precision="fp64", receivers_nt=None):
+        s = cls(wl.nx, wl.ny, wl.nz, wl.h, precision=precision, n_shots=wl.n_shots)
+        s.set_model(wl.lam, wl.mu, wl.rho, wl.solid)
+        s.set_fixed_nodes(wl.fixed)
+        s.set_dt(wl.dt)
+        s.set_sources(wl.src_node, wl.src_comp, wl.wavelet, wl.src_shot)
+        s.set_receivers(wl.rec_node, wl.nt if receivers_nt is None else receivers_nt)
+        return s
+
+    # --- stepping and data (device tensors)
+    def reset(self):
+        _check(_LIB.ovfem_reset(self._h))
+
+    def step(self, n=1):
+        _check(_LIB.ovfem_step(self._h, int(n)))
+
+    def synchronize(self):
+        _check(_LIB.ovfem_synchronize(self._h))
+
+    def matvec(self, u, out=None):
+        import torch
+        n = 3 * self.n_nodes
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=u.device)
+        _check(_LIB.ovfem_matvec(self._h, _dev_f64(u, n, "u"), _dev_f64(out, n, "out")))
+        return out
+
+    def get_wavefield(self, which=0, out=None):
+        import torch
+        n = 3 * self.n_nodes
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(_LIB.ovfem_get_wavefield(self._h, int(which), _dev_f64(out, n, "out")))
+        return out
+
+    def set_wavefield(self, un, unm1, step=0):
+        n = 3 * self.n_nodes
+        _check(_LIB.ovfem_set_wavefield(self._h, _dev_f64(un, n, "un"), _dev_f64(unm1, n, "unm1"), int(step)))
+
+    def get_traces(self, out=None):
+        import torch
+        n = self.n_shots * self.n_rec * 3 * self.rec_nt
+        if out is None:
+            out = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")[:n]
+        _check(_LIB.ovfem_get_traces(self._h, _dev_f64(out, n, "out") if n else None))
+        return out.view(self.n_shots, self.n_rec, 3, self.rec_nt)
+
+    def get_step(self):
+        v = ctypes.c_int64()
+        _check(_LIB.ovfem_get_step(self._h, ctypes.byref(v)))
+        return v.value

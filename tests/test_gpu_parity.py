@@ -1,0 +1,202 @@
+"""GPU parity: the HIP stepper (FP64 and INT8 paths) against the CPU oracle.
+
+Tolerances (the target for this path): relative L2 <= 1e-12 per matvec, <= 1e-9 on
+receiver traces after all steps.  Inputs are seeded (paper_2404_13683_amd.workloads).
+"""
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from paper_2404_13683_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "int8"]
+MATVEC_TOL = 1e-12
+TRACE_TOL = 1e-9
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _solver(w, prec):
+    from paper_2404_13683_amd.ovfem import Solver
+    return Solver.from_workload(w, precision=prec)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _random_medium(nx, ny, nz, seed, h=2.0, nt=60):
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    rho = rng.uniform(1800, 2600, shape)
+    vs = rng.uniform(400, 2000, shape)
+    lam, mu = wl.lame_from_velocities(2.0 * vs, vs, rho)
+    lam = lam * rng.uniform(0.8, 1.2, shape)
+    dt = wl.stable_dt(h, lam, mu, rho)
+    src = np.array([wl.node_id(nx // 2, ny // 2, nz, nx, ny)], np.int64)
+    return wl.Workload("random-medium", nx, ny, nz, h, lam, mu, rho, wl.box_fixed(nx, ny, nz), dt, nt,
+                       src, np.array([2], np.int32), np.array([0], np.int32),
+                       wl.ricker(nt, dt, 1.0 / (25 * dt))[None, :],
+                       wl.surface_nodes(rng, min(6, (nx + 1) * (ny + 1) - 1), nx, ny, nz,
+                                        margin=1 if min(nx, ny) > 2 else 0, exclude=src))
+
+
+def _gpu_matvec(w, prec, u):
+    torch = _torch()
+    s = _solver(w, prec)
+    ut = torch.from_numpy(np.ascontiguousarray(u).reshape(-1)).cuda()
+    out = s.matvec(ut).cpu().numpy().reshape(u.shape)
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dims", [(37, 23, 19), (1, 1, 1), (14, 15, 15), (15, 16, 16), (29, 30, 32), (2, 31, 3)])
+def test_matvec_random_vector(prec, dims):
+    nx, ny, nz = dims
+    w = _random_medium(nx, ny, nz, seed=nx * 10000 + ny * 100 + nz)
+    u = wl.random_field((nz + 1, ny + 1, nx + 1, 3), seed=7)
+    ref = oasm.matvec(u, w.lam, w.mu, w.h)
+    got = _gpu_matvec(w, prec, u)
+    err = _rel(got, ref)
+    print("matvec %s %s rel L2 %.3e" % (prec, dims, err))
+    assert err <= MATVEC_TOL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_matvec_wide_dynamic_range_and_zero(prec):
+    nx, ny, nz = 33, 20, 18
+    w = _random_medium(nx, ny, nz, seed=3)
+    rng = np.random.default_rng(11)
+    shape = (nz + 1, ny + 1, nx + 1, 3)
+    u = rng.standard_normal(shape) * 10.0 ** rng.uniform(-30, 30, shape)
+    ref = oasm.matvec(u, w.lam, w.mu, w.h)
+    assert _rel(_gpu_matvec(w, prec, u), ref) <= MATVEC_TOL
+    z = _gpu_matvec(w, prec, np.zeros(shape))
+    assert np.all(z == 0.0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_matvec_smooth_wavefield(prec):
+    """A propagated wavefield (smooth, strong cancellation in K u) instead of noise."""
+    w = _random_medium(30, 28, 24, seed=5, nt=80)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    _, u, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    ref = oasm.matvec(u, w.lam, w.mu, w.h)
+    err = _rel(_gpu_matvec(w, prec, u), ref)
+    print("smooth matvec %s rel L2 %.3e" % (prec, err))
+    assert err <= MATVEC_TOL
+
+
+def test_int8_not_less_accurate_than_fp64():
+    """Sec. 3, Table 3 pattern: the INT8 form is at least as close to the exact K u as FP64.
+
+    Exact reference at sampled nodes in rational arithmetic (inputs are exact binary
+    fractions, K_lam and K_mu exact rationals).
+    """
+    from fractions import Fraction
+
+    from oracle import element as el
+    nx, ny, nz = 20, 18, 17
+    w = _random_medium(nx, ny, nz, seed=9)
+    u = wl.random_field((nz + 1, ny + 1, nx + 1, 3), seed=21)
+    got = {p: _gpu_matvec(w, p, u) for p in PRECS}
+    Kl, Km = el.ovfem_reference_exact()
+    rng = np.random.default_rng(2)
+    errs = {p: [] for p in PRECS}
+    for _ in range(40):
+        i, j, k = (int(rng.integers(1, nx)), int(rng.integers(1, ny)), int(rng.integers(1, nz)))
+        exact = [Fraction(0)] * 3
+        for alpha in range(8):
+            di, dj, dk = alpha & 1, (alpha >> 1) & 1, (alpha >> 2) & 1
+            ei, ej, ek = i - di, j - dj, k - dk
+            ue = []
+            for b in range(8):
+                for c in range(3):
+                    ue.append(Fraction(float(u[ek + ((b >> 2) & 1), ej + ((b >> 1) & 1), ei + (b & 1), c])))
+            L = Fraction(float(w.lam[ek, ej, ei])) * Fraction(w.h)
+            M = Fraction(float(w.mu[ek, ej, ei])) * Fraction(w.h)
+            for c in range(3):
+                row = 3 * alpha + c
+                exact[c] += L * sum(Kl[row][q] * ue[q] for q in range(24)) + M * sum(Km[row][q] * ue[q] for q in range(24))
+        for p in PRECS:
+            for c in range(3):
+                errs[p].append(abs(float(Fraction(float(got[p][k, j, i, c])) - exact[c])) / abs(float(exact[c])))
+    med = {p: float(np.median(errs[p])) for p in PRECS}
+    print("median rel error vs exact:", med)
+    assert med["int8"] <= 1.5 * med["fp64"]
+    assert max(errs["int8"]) < 1e-13
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c1_homogeneous_traces(prec):
+    """Config: 16^3 homogeneous cube, 200 steps, centre z-force, 8 surface receivers."""
+    w = wl.homogeneous_c1()
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    s = _solver(w, prec)
+    s.step(w.nt)
+    tr = s.get_traces().cpu().numpy()[0]
+    u = s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape)
+    err_t, err_u = _rel(tr, ref), _rel(u, u_ref)
+    print("c1 %s traces %.3e wavefield %.3e" % (prec, err_t, err_u))
+    assert err_t <= TRACE_TOL and err_u <= TRACE_TOL
+    assert np.all(u[w.fixed.astype(bool)] == 0.0)
+    assert s.get_step() == w.nt
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_layered_ragged_grid_traces(prec):
+    w = wl.layered_c2(nx=41, ny=33, nz=26, nt=150, seed=12)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    s = _solver(w, prec)
+    s.step(w.nt)
+    tr = s.get_traces().cpu().numpy()[0]
+    u = s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape)
+    err_t, err_u = _rel(tr, ref), _rel(u, u_ref)
+    print("layered %s traces %.3e wavefield %.3e" % (prec, err_t, err_u))
+    assert err_t <= TRACE_TOL and err_u <= TRACE_TOL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_resume_is_bitwise_and_deterministic(prec):
+    w = wl.layered_c2(nx=24, ny=20, nz=18, nt=60, seed=13)
+    s = _solver(w, prec)
+    s.step(30)
+    un, unm1 = s.get_wavefield(0).clone(), s.get_wavefield(1).clone()
+    s.step(30)
+    full = s.get_wavefield(0).cpu().numpy()
+    tr_full = s.get_traces().cpu().numpy()
+    s.reset()
+    s.step(60)
+    again = s.get_wavefield(0).cpu().numpy()
+    assert np.array_equal(full, again)
+    s.reset()
+    s.set_wavefield(un, unm1, step=30)
+    s.step(30)
+    assert np.array_equal(s.get_wavefield(0).cpu().numpy(), full)
+    assert np.array_equal(s.get_traces().cpu().numpy()[..., 30:], tr_full[..., 30:])
+
+
+def test_invalid_dt_and_model_are_rejected():
+    from paper_2404_13683_amd.ovfem import OvfemError, Solver
+    w = wl.homogeneous_c1(nx=6, ny=6, nz=6)
+    s = Solver(6, 6, 6, w.h)
+    with pytest.raises(OvfemError):
+        s.step(1)  # no model yet
+    bad = w.mu.copy()
+    bad[1, 2, 3] = -1.0
+    with pytest.raises(OvfemError):
+        s.set_model(w.lam, bad, w.rho)
+    s.set_model(w.lam, w.mu, w.rho)
+    with pytest.raises(OvfemError):
+        s.set_dt(2.0 * w.h / 2000.0)  # twice the lattice limit
+    s.set_dt(w.dt)
+    with pytest.raises(OvfemError):
+        s.set_sources([10 ** 9], [2], np.ones((1, 4)))

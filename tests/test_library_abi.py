@@ -1,0 +1,60 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ovfem.h")
+LIB = os.path.join(ROOT, "paper_2404_13683_amd", "libovfem.so")
+PKG = os.path.join(ROOT, "paper_2404_13683_amd")
+
+
+def _declared():
+    text = open(HEADER).read()
+    decl = r"^\s*(?:ovfem_status|int32_t|const char\*)\s+(ovfem_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(decl, text, re.M)))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libovfem.so not built")
+
+
+@needs_lib
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@needs_lib
+def test_binding_signatures_cover_the_header():
+    from paper_2404_13683_amd import ovfem
+    assert sorted(ovfem.SIGNATURES) == _declared()
+
+
+@needs_lib
+def test_invalid_arguments_fail_before_touching_the_device():
+    from paper_2404_13683_amd import ovfem
+    lib = ovfem.lib()
+    h = ctypes.c_void_p()
+    assert lib.ovfem_create(None, 4, 4, 4, 1.0, 1, 0, None) == -1
+    assert lib.ovfem_create(ctypes.byref(h), 0, 4, 4, 1.0, 1, 0, None) == -1
+    assert b"positive" in lib.ovfem_last_error()
+    assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, -1.0, 1, 0, None) == -1
+    assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 1, 7, None) == -1
+    assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 2, 0, None) == -1
+    assert lib.ovfem_step(None, 1) == -1
+    assert lib.ovfem_destroy(None) == 0
+    assert lib.ovfem_version() >= 100
+
+
+def test_product_path_does_not_use_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
+                assert not re.search(r"import_module\(\s*['\"]oracle|#include\s+[<\"][^>\"]*oracle", text), f
