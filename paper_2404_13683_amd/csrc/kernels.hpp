@@ -1,33 +1,37 @@
 // HIP kernels (gfx950) of the OVFEM voxel stepper.
 //
-// One work-group of 256 threads owns a tile of 15 x 15 node columns and a chunk of
-// `tz` node planes.  It marches up through the chunk one element layer at a time.
-// For element layer k it stages node plane k+1 in LDS (plane k is already there),
-// computes the 16 x 16 elements whose corners touch the owned nodes (one halo
-// element on each side), keeps each element's contribution to plane k+1 in
-// registers, and sums the four in-plane contributions to every owned node of plane
-// k.  Plane k is then complete (element layers k-1 and k), so the central-difference
-// update of Sec. 2, Eq. (3) runs for it at once:
+// Work decomposition.  A work-group of 256 threads (4 waves) owns a tile of 15 x 15
+// node columns and a chunk of `tz` node planes, and marches up through the chunk one
+// element layer at a time.  For element layer k it stages node plane k+1 in LDS
+// (plane k is already there), computes the 16 x 16 elements whose corners touch the
+// owned nodes (one halo element on each side), keeps each element's contribution to
+// plane k+1 in registers for the next layer, and forms the in-plane sums of the
+// contributions to plane k.  Plane k is then complete (element layers k-1 and k) and
+// the central-difference update of Sec. 2, Eq. (3) runs for it at once:
 //     u^{n+1} = 2 u^n - u^{n-1} + dt^2 m^{-1} (F^n - (K u^n))   (zero where m^{-1} = 0).
-// Every node is summed by exactly one thread in a fixed order, so results are
-// bitwise reproducible (no atomics).
+// Every node is summed by one thread in a fixed order: results are bitwise
+// reproducible (no atomics).  Lanes of a wave map to rows of 16 elements along x, so
+// the two in-row neighbours of a node are combined with one DPP row shift.
 //
-// Element products, K_e u_e = h lam_e K_lam u_e + h mu_e K_mu u_e with integer
-// AL = 256 K_lam, AM = 128 K_mu (refmat.hpp):
+// Element products, K_e u_e = h lam_e K_lam u_e + h mu_e K_mu u_e with the integer
+// matrices AL = 256 K_lam, AM = 128 K_mu (refmat.hpp):
 //   * FP64 path: one thread per element, dense 24 x 24 products in FP64 with the
 //     integer matrices as compile-time constants (the paper's "OVFEM FP64").
-//   * INT8 path (Sec. 2, Eqs. (10)-(17), reworked for CDNA4): u is written as
-//     2^(E-62) q with q an integer, |q| <= 2^62, under one power-of-two exponent E per
-//     tile (the paper scales per element by s_e; a shared exponent lets a node's
-//     digits be computed once and reused by its 8 elements, and the extra bits keep
-//     every value within 2^9 of the tile maximum exact).  q is split into M = 8
-//     balanced base-256 digits d_j in [-128, 127] (the paper uses 8 sign-magnitude
-//     base-128 digits of a 56-bit integer).  The 48 x 24 matrix [AL; AM] times the
-//     digit panel of 16 elements runs on v_mfma_i32_16x16x32_i8.  Digits are taken
-//     pairwise from the top, C = A d_hi, C <<= 8, C += A d_lo, which stays below
-//     2^31 since |C| <= 384 * 128 * 257; the four group results are recombined in
-//     FP64 (Horner with factor 2^16), then scaled by h lam_e / 256 * 2^(E-62) and
-//     h mu_e / 128 * 2^(E-62).
+//   * INT8 path (Sec. 2, Eqs. (10)-(17), reworked for CDNA4).  u is written as
+//     2^(E-62) q, q = floor(u 2^(62-E)) an integer with |q| <= 2^62, under one
+//     power-of-two exponent E per tile (the paper scales each element by s_e; a
+//     shared exponent lets a node's slices be computed once for its 8 elements, and
+//     the 62 bits keep every value within 2^9 of the tile maximum exact).  q is split
+//     into M = 8 balanced base-256 digits d_j in [-128, 127] (the paper: 8
+//     sign-magnitude base-128 digits of a 56-bit integer).  The digit products with
+//     the 48 x 24 integer matrix [AL; AM] run on the matrix cores, two digits per
+//     FP32 accumulator: A (256 d_{2p+1}) + A (d_{2p} + 128) is accumulated by two
+//     v_mfma_f32_16x16x32_bf16.  Every operand is an integer of at most 8
+//     significant bits (exact in bf16) and every partial sum an integer below
+//     384 * 128 * 256 + 384 * 255 < 2^24 (exact in FP32), so the pair sum is exact;
+//     the +128 bias on the low digit drops out because each row of K sums to zero
+//     (rigid translations).  The four pair sums are recombined in FP64 (Horner with
+//     factor 2^16) and scaled by h lam_e / 256 * 2^(E-62) and h mu_e / 128 * 2^(E-62).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,23 +45,30 @@ constexpr int TE = 16;        // element columns per tile side
 constexpr int TN = TE - 1;    // owned node columns per tile side
 constexpr int PN = TE + 1;    // node columns per staged plane side
 constexpr int NTHR = 256;     // threads per work-group
-constexpr int NDIG = 8;       // balanced base-256 digits per value
+constexpr int NPAIR = 4;      // digit pairs (M = 8 digits)
 constexpr int QBITS = 62;     // fraction bits of q under the tile exponent
-constexpr int PP = 18;        // padded pitch (dwords) of a digit row
-constexpr int DPLANE = PN * NDIG * PP;  // dwords per staged digit plane
-constexpr int FPLANE = 3 * PN * PN;     // doubles per staged FP64 plane
-constexpr int EXP_NONE = -1000000;      // exponent of an all-zero tile
+constexpr int NODE_DW = 16;   // dwords of one staged node: 4 pairs x (hi, lo) x 2 dwords
+// digit plane layout [row q][pair p][hi/lo][column x][2 dwords]: the B operand of a
+// lane (its element's nodes x and x+1 in one row) is 16 contiguous bytes
+constexpr int DPLANE = PN * PN * NODE_DW;  // dwords per staged digit plane
+constexpr int DROW = NPAIR * 2 * PN * 2;   // dwords per staged digit row
+constexpr int FPLANE = 3 * PN * PN;        // doubles per staged FP64 plane
+constexpr int NEXTRA = PN * PN - NTHR;     // staged nodes beyond one per thread (33)
+constexpr int EXP_NONE = -1000000;         // exponent of an all-zero tile
 
-static_assert(kMaxRowAbs * 128 * 257 < 2147483647, "two-digit INT32 Horner group must not overflow");
+static_assert(kMaxRowAbs * 128 * 256 + kMaxRowAbs * 255 < (1 << 24),
+              "digit-pair sums must be exact in FP32");
 
 enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
 enum : int { PATH_FP64 = 0, PATH_INT8 = 1 };
 
-typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 struct Geom {
-  int nx, ny, nz;       // elements per axis
-  int tz;               // node planes per chunk
+  int nx, ny, nz;  // elements per axis
+  int tz;          // node planes per chunk
   int tiles_x, tiles_y, chunks;
   int n_wg;
 };
@@ -67,12 +78,11 @@ struct KArgs {
   const double* u;        // u^n, [node][3]
   double* uprev_next;     // in: u^{n-1}; out: u^{n+1} (same array)
   double* ku;             // MODE_MATVEC output K u, [node][3]
-  const double* lam_s;    // h lam / 256 per element (0 for removed voxels)
-  const double* mu_s;     // h mu / 128 per element
+  const double* mat;      // [element][2] = (h lam / 256, h mu / 128), 0 for removed voxels
   const double* acoef;    // dt^2 / m per node, 0 where the node does not move
   const int* exp_in;      // per tile: exponent e with max |u^n| < 2^e (INT8 path)
   int* exp_out;           // per tile: same for u^{n+1} (MODE_STEP)
-  const uint64_t* alane;  // INT8 A operands, [3 row tiles][64 lanes]
+  const v4u* alane;       // INT8 A operands, [3 row tiles][64 lanes] x 8 bf16
   const int* src_ptr;     // [n_wg + 1] CSR of sources per tile
   const int* src_node;    // node id of each listed source
   const int* src_comp;    // component
@@ -94,68 +104,101 @@ __device__ inline int logical_tile(int b, int n_wg) {
   return xcd < rem ? xcd * (n8 + 1) + slot : rem * (n8 + 1) + (xcd - rem) * n8 + slot;
 }
 
-__device__ inline long long node_index(const Geom& g, int X, int Y, int Z) {
-  return (long long)X + (long long)(g.nx + 1) * ((long long)Y + (long long)(g.ny + 1) * Z);
-}
-
 struct D3 {
   double v[3];
 };
 
-// The three components of node (X, Y, Z) of v, zero outside the grid.
-__device__ inline D3 load_node(const Geom& g, const double* v, int X, int Y, int Z) {
-  D3 r = {{0.0, 0.0, 0.0}};
-  if (X >= 0 && Y >= 0 && Z >= 0 && X <= g.nx && Y <= g.ny && Z <= g.nz) {
-    const double* p = v + 3 * node_index(g, X, Y, Z);
-    r.v[0] = p[0];
-    r.v[1] = p[1];
-    r.v[2] = p[2];
-  }
-  return r;
-}
-
-// Eight balanced base-256 digits of q = rint(u 2^(62-E)) for the three components,
-// packed per digit as bytes (c0, c1, c2, 0): the B-operand layout of the MFMA.
-// (lam_s, mu_s) of element (X, Y, Z), zero outside the grid.
-__device__ inline D3 load_material(const Geom& g, const double* lam_s, const double* mu_s, int X, int Y, int Z) {
-  D3 r = {{0.0, 0.0, 0.0}};
-  if (X >= 0 && Y >= 0 && Z >= 0 && X < g.nx && Y < g.ny && Z < g.nz) {
-    const long long e = (long long)X + (long long)g.nx * ((long long)Y + (long long)g.ny * Z);
-    r.v[0] = lam_s[e];
-    r.v[1] = mu_s[e];
-  }
-  return r;
-}
-
-struct DigitWords {
-  uint32_t w[NDIG];
+// A staged node column: in-plane validity and the byte offset of the node within a
+// plane of nodal vectors (clamped to node 0 when the column lies outside the grid).
+struct NodeRef {
+  bool xy_ok;
+  uint32_t off;  // byte offset of [node][3] within one plane
 };
 
-__device__ inline DigitWords digit_words(const D3& u, int E) {
+__device__ inline NodeRef node_ref(const Geom& g, int X, int Y) {
+  NodeRef r;
+  r.xy_ok = X >= 0 && Y >= 0 && X <= g.nx && Y <= g.ny;
+  r.off = r.xy_ok ? (uint32_t)(24 * (X + (g.nx + 1) * Y)) : 0u;
+  return r;
+}
+
+// Node of a plane: the load always hits valid memory; values outside the grid are 0.
+__device__ inline D3 load_node(const unsigned char* plane, const NodeRef& n, bool z_ok) {
+  const double* p = reinterpret_cast<const double*>(plane + n.off);
+  const bool ok = n.xy_ok && z_ok;
+  D3 r;
+  r.v[0] = ok ? p[0] : 0.0;
+  r.v[1] = ok ? p[1] : 0.0;
+  r.v[2] = ok ? p[2] : 0.0;
+  return r;
+}
+
+// An element column: validity and the byte offset of [element][2] within one layer.
+struct ElemRef {
+  bool xy_ok;
+  uint32_t off;
+};
+
+__device__ inline ElemRef elem_ref(const Geom& g, int X, int Y) {
+  ElemRef r;
+  r.xy_ok = X >= 0 && Y >= 0 && X < g.nx && Y < g.ny;
+  r.off = r.xy_ok ? (uint32_t)(16 * (X + g.nx * Y)) : 0u;
+  return r;
+}
+
+// (h lam / 256, h mu / 128) of an element of a layer, zero outside the grid.
+__device__ inline double2 load_material(const unsigned char* layer, const ElemRef& e, bool z_ok) {
+  const double2 m = *reinterpret_cast<const double2*>(layer + e.off);
+  const bool ok = e.xy_ok && z_ok;
+  return make_double2(ok ? m.x : 0.0, ok ? m.y : 0.0);
+}
+
+// bf16 words of two floats with at most 8 significant bits (truncation is exact).
+__device__ inline uint32_t bf16_pair(float lo, float hi) {
+  return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
+}
+
+// Stage one node's INT8 slices: q ~ u 2^(62-E) per component, the biased bytes
+// e_j = d_j + 128 of q + sum_j 128 * 256^j, and per digit pair p the bf16 B-operand
+// words (c0, c1), (c2, 0) of 256 d_{2p+1} (hi) and of e_{2p} (lo).  dst points at the
+// node's first word in its row ([p][hi/lo][x][2] with x stride 2 dwords).
+__device__ inline void stage_digits(const D3& u, int E, uint32_t* dst) {
   uint32_t lo[3], hi[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double x = rint(ldexp(u.v[c], QBITS - E));     // |x| <= 2^62, exact integer
+    // q = floor(x) up to one unit (the low word is truncated after at most one
+    // rounding of x - hd 2^32), |q| <= 2^62
+    const double x = ldexp(u.v[c], QBITS - E);
     const double hd = floor(x * 0x1p-32);                 // exact, |hd| <= 2^30
-    const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);  // in [0, 2^32), exact
+    const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);  // in [0, 2^32)
     const uint64_t q = ((uint64_t)(uint32_t)(int)hd << 32) | lo_u;  // two's complement
-    // q + sum_j 128 * 256^j (mod 2^64) has the digits (d_j + 128) as its bytes
-    const uint64_t d = q + 0x8080808080808080ull;
-    lo[c] = (uint32_t)d ^ 0x80808080u;
-    hi[c] = (uint32_t)(d >> 32) ^ 0x80808080u;
+    const uint64_t d = q + 0x8080808080808080ull;        // bytes are d_j + 128
+    lo[c] = (uint32_t)d;
+    hi[c] = (uint32_t)(d >> 32);
   }
-  DigitWords r;
+  uint32_t w[NODE_DW];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int sh = 8 * j;
-    r.w[j] = ((lo[0] >> sh) & 0xffu) | (((lo[1] >> sh) & 0xffu) << 8) | (((lo[2] >> sh) & 0xffu) << 16);
+  for (int p = 0; p < NPAIR; ++p) {
+    const int bh = (2 * p + 1) & 3, bl = (2 * p) & 3;  // byte positions of the pair
+    float fh[3], fl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint32_t s = p < 2 ? lo[c] : hi[c];
+      fh[c] = fmaf((float)((s >> (8 * bh)) & 0xffu), 256.0f, -32768.0f);  // 256 d_hi, exact
+      fl[c] = (float)((s >> (8 * bl)) & 0xffu);                            // d_lo + 128
+    }
+    w[4 * p + 0] = bf16_pair(fh[0], fh[1]);
+    w[4 * p + 1] = __float_as_uint(fh[2]) >> 16;
+    w[4 * p + 2] = bf16_pair(fl[0], fl[1]);
+    w[4 * p + 3] = __float_as_uint(fl[2]) >> 16;
   }
 #pragma unroll
-  for (int j = 4; j < NDIG; ++j) {
-    const int sh = 8 * (j - 4);
-    r.w[j] = ((hi[0] >> sh) & 0xffu) | (((hi[1] >> sh) & 0xffu) << 8) | (((hi[2] >> sh) & 0xffu) << 16);
-  }
-  return r;
+  for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+    for (int hl = 0; hl < 2; ++hl) {
+      uint2* d2 = reinterpret_cast<uint2*>(dst + (2 * p + hl) * PN * 2);
+      *d2 = make_uint2(w[4 * p + 2 * hl], w[4 * p + 2 * hl + 1]);
+    }
 }
 
 // Per-element FP64 product: y = lam_s AL ue + mu_s AM ue.
@@ -172,15 +215,28 @@ __device__ inline void element_fp64(const double ue[24], double lam_s, double mu
   }
 }
 
-// Wave-wide max of a non-negative double.
+// v of the lane one to the left within its row of 16 lanes (0 for the first lane).
+__device__ inline double row_shift_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x111, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x111, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Values of row 1 moved to row 0 and of row 3 to row 2 (rows of 16 lanes).
+__device__ inline double rows_down(double v) {
+  const int lo = (int)__double2loint(v), hi = (int)__double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[1], (int)l[1]);
+}
+
 __device__ inline double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
   return v;
 }
 
-// Work-group max of |u| over owned nodes -> tile exponent (shared by the stepper
-// and the exponent initialisation kernel).
+// Work-group max of |u| over owned nodes -> tile exponent e with max < 2^e.
 __device__ inline void write_tile_exponent(double local_max, int* dst, double* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   local_max = wave_max(local_max);
@@ -189,31 +245,32 @@ __device__ inline void write_tile_exponent(double local_max, int* dst, double* r
   if (threadIdx.x == 0) {
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     int e = EXP_NONE;
-    if (m > 0.0) frexp(m, &e);  // m < 2^e
+    if (m > 0.0) frexp(m, &e);
     *dst = e;
   }
 }
 
 template <int PATH, int MODE>
-__global__ void __launch_bounds__(NTHR) ovfem_layer_kernel(KArgs A) {
-  const Geom& g = A.g;
+__global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_kernel(KArgs A) {
+  const Geom g = A.g;
   const int wg = logical_tile(blockIdx.x, g.n_wg);
   const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
   const int x0 = tx * TN, y0 = ty * TN, z0 = tzc * g.tz;
   const int z1 = min(z0 + g.tz, g.nz + 1);  // owned planes [z0, z1)
-  const int t = threadIdx.x;
-  const int ta = t & 15, tb = t >> 4;       // element column (ta, tb) / main staged node (ta+1, tb+1)
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int ta = t & 15, tb = t >> 4;       // element column (ta, tb); main staged node (ta+1, tb+1)
 
-  __shared__ double acc[4 * 3 * TE * TE];                  // [c2][c][b][a] in-plane corner sums
+  // in-plane node sums: lsum[q] from elements of row q, usum[q-1] from elements of row q-1
+  __shared__ double lsum[TE * 3 * TE];  // [q][c][p], q = 0..15
+  __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
   __shared__ double red[4];
-  // staged planes: FP64 values or INT8 digit words, two slots
+  __shared__ __attribute__((aligned(16))) double matl[PATH == PATH_INT8 ? 2 * NTHR : 2];  // INT8: [b][a] material
   constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : 2 * DPLANE * 4;
   __shared__ __attribute__((aligned(16))) unsigned char ring_raw[RING_BYTES];
-  __shared__ double mat[PATH == PATH_INT8 ? 2 * TE * TE : 2];  // INT8: [b][a] (lam_s, mu_s)
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
 
-  // ---- tile exponent (INT8): max over the 27 neighbouring tiles that own the staged nodes
+  // ---- tile exponent (INT8): max over the 27 tiles owning the staged nodes
   int E = 0;
   if (PATH == PATH_INT8) {
     int e = EXP_NONE;
@@ -226,41 +283,52 @@ __global__ void __launch_bounds__(NTHR) ovfem_layer_kernel(KArgs A) {
         }
     E = e == EXP_NONE ? 0 : e;
   }
-
-  // INT8 operands: lane's A fragments for the three 16-row tiles
-  const int lane = t & 63, wave = t >> 6;
-  uint64_t a_frag[3] = {0, 0, 0};
+  v8bf a_frag[3];
   if (PATH == PATH_INT8) {
-    a_frag[0] = A.alane[lane];
-    a_frag[1] = A.alane[64 + lane];
-    a_frag[2] = A.alane[128 + lane];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a_frag[i] = __builtin_bit_cast(v8bf, A.alane[i * 64 + lane]);
   }
 
-  // staged node positions: main node (ta+1, tb+1); threads 0..32 also stage a halo node
+  // staged nodes: main node (ta+1, tb+1); the first 33 lanes of the last wave stage
+  // one more (the row q = 0 and the column p = 0 of the plane)
+  const int xi = t - (NTHR - 64);
+  const bool has_extra = xi >= 0 && xi < NEXTRA;
   const int mp = ta + 1, mq = tb + 1;
-  const int xp = t < 17 ? t : 0, xq = t < 17 ? 0 : t - 16;  // (p, q) of the extra node
-  const bool has_extra = t < 33;
-  const bool owner = ta < TN && tb < TN;  // owns node (ta+1, tb+1) = (x0+ta, y0+tb)
-  const int OX = x0 + ta, OY = y0 + tb;
-  const bool owner_in = owner && OX <= g.nx && OY <= g.ny;
+  const int xp = xi < PN ? xi : 0, xq = xi < PN ? 0 : xi - (PN - 1);
+  const NodeRef main_ref = node_ref(g, x0 - 1 + mp, y0 - 1 + mq);
+  const NodeRef extra_ref = node_ref(g, x0 - 1 + xp, y0 - 1 + xq);
+  const ElemRef elem = elem_ref(g, x0 - 1 + ta, y0 - 1 + tb);
+  const bool owner = ta < TN && tb < TN;  // owns node (x0+ta, y0+tb) = plane (ta+1, tb+1)
+  const bool owner_in = owner && main_ref.xy_ok;
+  const size_t plane_bytes = (size_t)24 * (g.nx + 1) * (g.ny + 1);
+  const size_t layer_bytes = (size_t)16 * g.nx * g.ny;
+  const unsigned char* u_base = reinterpret_cast<const unsigned char*>(A.u);
+  const unsigned char* mat_base = reinterpret_cast<const unsigned char*>(A.mat);
 
-  // register pipeline of the main node's u^n (plane rel r = Z - (z0-1))
-  D3 u_main_next = {{0.0, 0.0, 0.0}}, u_extra_next = {{0.0, 0.0, 0.0}};
-  D3 u_own_bot = {{0.0, 0.0, 0.0}}, u_own_top = {{0.0, 0.0, 0.0}};
-  double top_prev[12];  // FP64: this element's contribution to the plane above (4 corners x 3)
-  double top_prev8[4][3];
+  D3 u_main_next, u_extra_next = {{0.0, 0.0, 0.0}};
+  D3 u_own_top = {{0.0, 0.0, 0.0}}, u_own_bot;
+  double top_f[12];    // FP64: this element's contribution to the plane above
+  double top_i[4][3];  // INT8: per tile row, this lane's corner contribution to the plane above
 #pragma unroll
-  for (int i = 0; i < 12; ++i) top_prev[i] = 0.0;
+  for (int i = 0; i < 12; ++i) top_f[i] = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) top_prev8[i][0] = top_prev8[i][1] = top_prev8[i][2] = 0.0;
-  D3 mat_next = {{0.0, 0.0, 0.0}};  // (lam_s, mu_s) of element (ta, tb) of the next layer
+  for (int i = 0; i < 4; ++i) top_i[i][0] = top_i[i][1] = top_i[i][2] = 0.0;
+  double2 mat_next;
   double tile_max = 0.0;
+  const int src_lo = A.src_ptr[wg], src_hi = A.src_ptr[wg + 1];
+  const int rec_lo = A.rec_ptr[wg], rec_hi = A.rec_ptr[wg + 1];
 
   const int nrel = z1 - z0 + 2;  // staged planes z0-1 .. z1
   auto fetch = [&](int rel) {
     const int Z = z0 - 1 + rel;
-    u_main_next = load_node(g, A.u, x0 - 1 + mp, y0 - 1 + mq, Z);
-    if (has_extra) u_extra_next = load_node(g, A.u, x0 - 1 + xp, y0 - 1 + xq, Z);
+    const bool z_ok = Z >= 0 && Z <= g.nz;
+    const unsigned char* plane = u_base + (size_t)(z_ok ? Z : 0) * plane_bytes;
+    u_main_next = load_node(plane, main_ref, z_ok);
+    if (has_extra) u_extra_next = load_node(plane, extra_ref, z_ok);
+  };
+  auto fetch_mat = [&](int k) {
+    const bool z_ok = k >= 0 && k < g.nz;
+    mat_next = load_material(mat_base + (size_t)(z_ok ? k : 0) * layer_bytes, elem, z_ok);
   };
   auto stage = [&](int slot) {
     if (PATH == PATH_FP64) {
@@ -272,132 +340,153 @@ __global__ void __launch_bounds__(NTHR) ovfem_layer_kernel(KArgs A) {
         for (int c = 0; c < 3; ++c) P[(c * PN + xq) * PN + xp] = u_extra_next.v[c];
     } else {
       uint32_t* P = ringd + slot * DPLANE;
-      const DigitWords w = digit_words(u_main_next, E);
-#pragma unroll
-      for (int j = 0; j < NDIG; ++j) P[(mq * NDIG + j) * PP + mp] = w.w[j];
-      if (has_extra) {
-        const DigitWords wx = digit_words(u_extra_next, E);
-#pragma unroll
-        for (int j = 0; j < NDIG; ++j) P[(xq * NDIG + j) * PP + xp] = wx.w[j];
-      }
+      stage_digits(u_main_next, E, P + mq * DROW + 2 * mp);
+      if (has_extra) stage_digits(u_extra_next, E, P + xq * DROW + 2 * xp);
     }
   };
 
-  // prologue: plane rel 0 staged, plane rel 1 in registers
   fetch(0);
   stage(0);
   fetch(1);
-  mat_next = load_material(g, A.lam_s, A.mu_s, x0 - 1 + ta, y0 - 1 + tb, z0 - 1);
+  fetch_mat(z0 - 1);
 
   for (int it = 0; it + 1 < nrel; ++it) {
-    // element layer k = z0 - 1 + it uses planes rel it (slot it&1) and rel it+1
-    const int k = z0 - 1 + it;
+    const int k = z0 - 1 + it;  // element layer: planes rel it (slot it&1) and it+1
     const int bot = it & 1, top = (it + 1) & 1;
     u_own_bot = u_own_top;
     u_own_top = u_main_next;
     stage(top);
-    const double lam_e = mat_next.v[0], mu_e = mat_next.v[1];
+    const double2 mat_e = mat_next;
     if (PATH == PATH_INT8) {
-      mat[2 * t] = lam_e;
-      mat[2 * t + 1] = mu_e;
+      matl[2 * t] = mat_e.x;
+      matl[2 * t + 1] = mat_e.y;
     }
-    if (it + 2 < nrel) fetch(it + 2);
-    if (it + 2 < nrel) mat_next = load_material(g, A.lam_s, A.mu_s, x0 - 1 + ta, y0 - 1 + tb, k + 1);
-    // owned plane rel it (Z = k) update operands
-    const int Z = k;
+    if (it + 2 < nrel) {
+      fetch(it + 2);
+      fetch_mat(k + 1);
+    }
     const bool do_node = it >= 1 && owner_in;
-    long long nid = 0;
-    double up[3] = {0, 0, 0}, ac = 0.0;
-    if (do_node) {
-      nid = node_index(g, OX, OY, Z);
-      if (MODE == MODE_STEP) {
-        const double* pp = A.uprev_next + 3 * nid;
-        up[0] = pp[0];
-        up[1] = pp[1];
-        up[2] = pp[2];
-        ac = A.acoef[nid];
-      }
+    const size_t node_off = (size_t)k * plane_bytes + main_ref.off;  // byte offset of owned node
+    double up[3] = {0.0, 0.0, 0.0}, ac = 0.0;
+    if (do_node && MODE == MODE_STEP) {
+      const double* pp = reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.uprev_next) + node_off);
+      up[0] = pp[0];
+      up[1] = pp[1];
+      up[2] = pp[2];
+      ac = *reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.acoef) +
+                                            (size_t)k * (plane_bytes / 3) + main_ref.off / 3);
     }
+    const bool layer_ok = k >= 0 && k < g.nz;
     __syncthreads();
 
-    // ---- element layer k
+    // ---- element layer k -> in-plane sums for plane k
     if (PATH == PATH_FP64) {
-      const double* Pb = ringf + bot * FPLANE;
-      const double* Pt = ringf + top * FPLANE;
-      double ue[24];
-#pragma unroll
-      for (int alpha = 0; alpha < 8; ++alpha) {
-        const int di = alpha & 1, dj = (alpha >> 1) & 1, dk = alpha >> 2;
-        const double* P = dk ? Pt : Pb;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PN + tb + dj) * PN + ta + di];
-      }
       double y[24];
-      element_fp64(ue, lam_e, mu_e, y);
+      if (layer_ok) {
+        const double* Pb = ringf + bot * FPLANE;
+        const double* Pt = ringf + top * FPLANE;
+        double ue[24];
 #pragma unroll
-      for (int c2 = 0; c2 < 4; ++c2)
+        for (int alpha = 0; alpha < 8; ++alpha) {
+          const int di = alpha & 1, dj = (alpha >> 1) & 1, dk = alpha >> 2;
+          const double* P = dk ? Pt : Pb;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc[((c2 * 3 + c) * TE + tb) * TE + ta] = y[3 * c2 + c] + top_prev[3 * c2 + c];
-          top_prev[3 * c2 + c] = y[3 * (c2 + 4) + c];
+          for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PN + tb + dj) * PN + ta + di];
         }
+        element_fp64(ue, mat_e.x, mat_e.y, y);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 24; ++i) y[i] = 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v0 = y[c] + top_f[c], v1 = y[3 + c] + top_f[3 + c];
+        const double v2 = y[6 + c] + top_f[6 + c], v3 = y[9 + c] + top_f[9 + c];
+        lsum[(tb * 3 + c) * TE + ta] = v0 + row_shift_right(v1);  // node (ta, tb)
+        usum[(tb * 3 + c) * TE + ta] = v2 + row_shift_right(v3);  // node (ta, tb + 1)
+      }
+#pragma unroll
+      for (int i = 0; i < 12; ++i) top_f[i] = y[12 + i];
     } else {
-      const int ja = lane & 15, G = lane >> 4;
+      const int ja = lane & 15, G = lane >> 4;  // element column; lane group
       const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * DPLANE;
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int b = 4 * wave + tt;
-        const uint32_t* P = Pin + (b + (G & 1)) * NDIG * PP + ja;
-        uint64_t B[NDIG];
+        double ybot[3] = {0.0, 0.0, 0.0}, ytop[3] = {0.0, 0.0, 0.0};
+        if (layer_ok) {
+          const double2 me = *reinterpret_cast<const double2*>(matl + 2 * (b * TE + ja));
+          const uint32_t* P = Pin + (b + (G & 1)) * DROW + 2 * ja;
+          double R[12];
 #pragma unroll
-        for (int j = 0; j < NDIG; ++j) B[j] = (uint64_t)P[j * PP] | ((uint64_t)P[j * PP + 1] << 32);
-        double R[12];
+          for (int p = NPAIR - 1; p >= 0; --p) {
+            // the lane's eight K slots: (c0, c1, c2, 0) of node ja, then of node ja+1
+            const uint2* ph = reinterpret_cast<const uint2*>(P + (2 * p) * PN * 2);
+            const uint2* pl = reinterpret_cast<const uint2*>(P + (2 * p + 1) * PN * 2);
+            const uint2 h0 = ph[0], h1 = ph[1], l0 = pl[0], l1 = pl[1];
+            const v4u bh = {h0.x, h0.y, h1.x, h1.y};
+            const v4u bl = {l0.x, l0.y, l1.x, l1.y};
+            const v8bf Bh = __builtin_bit_cast(v8bf, bh), Bl = __builtin_bit_cast(v8bf, bl);
+            const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+            v4f c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[0], Bh, z, 0, 0, 0);
+            v4f c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[1], Bh, z, 0, 0, 0);
+            v4f c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bh, z, 0, 0, 0);
+            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[0], Bl, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[1], Bl, c1, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bl, c2, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 12; ++r) R[r] = 0.0;
-        // digit pairs from the top: (7,6), (5,4), (3,2), (1,0)
+            for (int r = 0; r < 4; ++r) {
+              if (p == NPAIR - 1) {
+                R[r] = (double)c0[r];
+                R[4 + r] = (double)c1[r];
+                R[8 + r] = (double)c2[r];
+              } else {
+                R[r] = fma(R[r], 65536.0, (double)c0[r]);
+                R[4 + r] = fma(R[4 + r], 65536.0, (double)c1[r]);
+                R[8 + r] = fma(R[8 + r], 65536.0, (double)c2[r]);
+              }
+            }
+          }
+          // output s = 4 * row tile + reg: s < 6 rows of AL, s >= 6 rows of AM;
+          // dk = (s % 6) / 3, c = s % 3, at corner G + 4 dk
+          const double sl = ldexp(me.x, E - QBITS), sm = ldexp(me.y, E - QBITS);
 #pragma unroll
-        for (int pr = 3; pr >= 0; --pr) {
-          const int jh = 2 * pr + 1, jl = 2 * pr;
-          const v4i z = {0, 0, 0, 0};
-          v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)a_frag[0], (long)B[jh], z, 0, 0, 0);
-          v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)a_frag[1], (long)B[jh], z, 0, 0, 0);
-          v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)a_frag[2], (long)B[jh], z, 0, 0, 0);
-          c0 = c0 << 8;
-          c1 = c1 << 8;
-          c2 = c2 << 8;
-          c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)a_frag[0], (long)B[jl], c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)a_frag[1], (long)B[jl], c1, 0, 0, 0);
-          c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)a_frag[2], (long)B[jl], c2, 0, 0, 0);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            R[r] = fma(R[r], 65536.0, (double)c0[r]);
-            R[4 + r] = fma(R[4 + r], 65536.0, (double)c1[r]);
-            R[8 + r] = fma(R[8 + r], 65536.0, (double)c2[r]);
+          for (int c = 0; c < 3; ++c) {
+            ybot[c] = R[c] * sl + R[6 + c] * sm;
+            ytop[c] = R[3 + c] * sl + R[9 + c] * sm;
           }
         }
-        // output s = 4 * tile + reg: s < 6 from AL, s >= 6 from AM; dk = (s % 6) / 3, c = s % 3
-        const double sl = ldexp(mat[2 * (b * TE + ja)], E - QBITS);
-        const double sm = ldexp(mat[2 * (b * TE + ja) + 1], E - QBITS);
+        // lane (ja, G) holds corner G of element (ja, b): node (ja + (G & 1), b + (G >> 1)).
+        // Each in-plane node of the row gets two terms: the even lanes store, then the
+        // odd lanes add (LDS operations of one wave complete in order; two addends
+        // commute exactly, so the sum does not depend on the hardware's lane order).
+        double v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double ybot = R[c] * sl + R[6 + c] * sm;
-          const double ytop = R[3 + c] * sl + R[9 + c] * sm;
-          acc[((G * 3 + c) * TE + b) * TE + ja] = ybot + top_prev8[tt][c];
-          top_prev8[tt][c] = ytop;
+          v[c] = ybot[c] + top_i[tt][c];
+          top_i[tt][c] = ytop[c];
         }
-        __builtin_amdgcn_sched_barrier(0);  // keep tiles apart: bounds live registers
+        double* dst = (G >> 1 ? usum : lsum) + b * 3 * TE + ja + (G & 1);
+        if ((G & 1) == 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) dst[c * TE] = v[c];
+        }
+        if ((G & 1) == 1 && ja < TE - 1) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) __hip_atomic_fetch_add(dst + c * TE, v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep tile rows apart: bounds live registers
       }
     }
     __syncthreads();
 
     // ---- node phase for plane Z = k (owned when it >= 1)
     if (do_node) {
+      const int p = ta + 1, q = tb + 1;
       double f[3];
-      const int a = ta, b = tb;
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        f[c] = acc[((3 * 3 + c) * TE + b) * TE + a] + acc[((2 * 3 + c) * TE + b) * TE + a + 1] +
-               acc[((1 * 3 + c) * TE + b + 1) * TE + a] + acc[((0 * 3 + c) * TE + b + 1) * TE + a + 1];
+      for (int c = 0; c < 3; ++c) f[c] = lsum[(q * 3 + c) * TE + p] + usum[((q - 1) * 3 + c) * TE + p];
+      const long long nid = (long long)k * (g.nx + 1) * (g.ny + 1) + main_ref.off / 24;
       if (MODE == MODE_MATVEC) {
         double* o = A.ku + 3 * nid;
         o[0] = f[0];
@@ -405,8 +494,7 @@ __global__ void __launch_bounds__(NTHR) ovfem_layer_kernel(KArgs A) {
         o[2] = f[2];
       } else {
         double F[3] = {0.0, 0.0, 0.0};
-        const int s0 = A.src_ptr[wg], s1 = A.src_ptr[wg + 1];
-        for (int s = s0; s < s1; ++s)
+        for (int s = src_lo; s < src_hi; ++s)
           if (A.src_node[s] == (int)nid && A.step < A.src_nt) {
             const double w = A.wavelet[(long long)A.src_row[s] * A.src_nt + A.step];
             const int sc = A.src_comp[s];
@@ -423,8 +511,7 @@ __global__ void __launch_bounds__(NTHR) ovfem_layer_kernel(KArgs A) {
         o[1] = un[1];
         o[2] = un[2];
         tile_max = fmax(tile_max, fmax(fabs(un[0]), fmax(fabs(un[1]), fabs(un[2]))));
-        const int r0 = A.rec_ptr[wg], r1 = A.rec_ptr[wg + 1];
-        for (int r = r0; r < r1; ++r)
+        for (int r = rec_lo; r < rec_hi; ++r)
           if (A.rec_node[r] == (int)nid && A.step < A.rec_nt) {
             double* tr = A.traces + (long long)A.rec_idx[r] * 3 * A.rec_nt + A.step;
             tr[0] = un[0];
@@ -448,7 +535,7 @@ __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const doub
   double m = 0.0;
   if (ta < TN && tb < TN && X <= g.nx && Y <= g.ny)
     for (int Z = z0; Z < z1; ++Z) {
-      const double* p = u + 3 * node_index(g, X, Y, Z);
+      const double* p = u + 3 * ((long long)X + (long long)(g.nx + 1) * ((long long)Y + (long long)(g.ny + 1) * Z));
       m = fmax(m, fmax(fabs(p[0]), fmax(fabs(p[1]), fabs(p[2]))));
     }
   write_tile_exponent(m, exp_out + wg, red);

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ovfem.h"
+#include "ovfem.h"
 #include "kernels.hpp"
 
 using namespace ovfem;
@@ -103,26 +103,29 @@ double max_eigenvalue(std::vector<double> a, int n) {
   return m;
 }
 
-// INT8 A fragments: lane l of row tile t holds A[i = l % 16][k = 8 (l / 16) .. + 7] of
-// the 16 x 32 tile.  Row i of tile t is output s = 4 t + i % 4 for in-plane corner
+// INT8 A fragments (bf16): lane l of row tile t holds A[i = l % 16][k = 8 (l / 16) .. + 7]
+// of the 16 x 32 tile.  Row i of tile t is output s = 4 t + i % 4 for in-plane corner
 // G = i / 4: s < 6 are rows of AL, s >= 6 rows of AM, at corner G + 4 ((s % 6) / 3)
 // and component s % 3.  Column k is (node k / 4, component k % 4), component 3 padding.
-std::vector<uint64_t> make_alane() {
-  std::vector<uint64_t> out(3 * 64);
+// Entries are integers of magnitude <= 98, exact in bf16.
+std::vector<uint32_t> make_alane() {
+  std::vector<uint32_t> out(3 * 64 * 4);
   for (int t = 0; t < 3; ++t)
     for (int l = 0; l < 64; ++l) {
       const int i = l % 16, kg = l / 16;
       const int G = i / 4, s = 4 * t + i % 4;
       const int which = s / 6, dk = (s % 6) / 3, c = s % 3;
       const int m = 3 * (G + 4 * dk) + c;
-      uint64_t w = 0;
       for (int q = 0; q < 8; ++q) {
         const int k = 8 * kg + q, node = k / 4, cp = k % 4;
         int v = 0;
         if (cp < 3) v = which == 0 ? kRef.AL[m][3 * node + cp] : kRef.AM[m][3 * node + cp];
-        w |= (uint64_t)(uint8_t)(int8_t)v << (8 * q);
+        const float f = (float)v;
+        uint32_t bits;
+        std::memcpy(&bits, &f, 4);
+        const uint32_t bf = bits >> 16;  // exact: |v| <= 127 has <= 7 significant bits
+        out[(t * 64 + l) * 4 + q / 2] |= bf << (16 * (q % 2));
       }
-      out[t * 64 + l] = w;
     }
   return out;
 }
@@ -141,11 +144,11 @@ struct ovfem_solver {
 
   DevBuf<double> u[2];
   int cur = 0;  // u[cur] = u^n, u[cur ^ 1] = u^{n-1}
-  DevBuf<double> lam_s, mu_s, acoef;
+  DevBuf<double> mat, acoef;  // mat: [element][2] = (h lam / 256, h mu / 128)
   DevBuf<int> expo[2], expo_tmp;
   int exp_cur = 0;
   bool exp_valid = false;
-  DevBuf<uint64_t> alane;
+  DevBuf<uint32_t> alane;
 
   DevBuf<int> src_ptr, src_node, src_comp, src_row;
   DevBuf<double> wavelet;
@@ -164,8 +167,7 @@ struct ovfem_solver {
     (void)hipStreamSynchronize(stream);
     u[0].free();
     u[1].free();
-    lam_s.free();
-    mu_s.free();
+    mat.free();
     acoef.free();
     expo[0].free();
     expo[1].free();
@@ -210,10 +212,9 @@ struct ovfem_solver {
   KArgs base_args() const {
     KArgs A{};
     A.g = geom;
-    A.lam_s = lam_s.p;
-    A.mu_s = mu_s.p;
+    A.mat = mat.p;
     A.acoef = acoef.p;
-    A.alane = alane.p;
+    A.alane = reinterpret_cast<const v4u*>(alane.p);
     A.src_ptr = src_ptr.p;
     A.src_node = src_node.p;
     A.src_comp = src_comp.p;
@@ -317,15 +318,14 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
       g.n_wg = g.tiles_x * g.tiles_y * g.chunks;
       s->u[0].alloc(3 * s->n_nodes);
       s->u[1].alloc(3 * s->n_nodes);
-      s->lam_s.alloc(s->n_elem);
-      s->mu_s.alloc(s->n_elem);
+      s->mat.alloc(2 * s->n_elem);
       s->acoef.alloc(s->n_nodes);
       s->expo[0].alloc(g.n_wg);
       s->expo[1].alloc(g.n_wg);
       s->expo_tmp.alloc(g.n_wg);
       auto al = make_alane();
       s->alane.alloc(al.size());
-      OVFEM_HIP(hipMemcpyAsync(s->alane.p, al.data(), al.size() * 8, hipMemcpyHostToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(s->alane.p, al.data(), al.size() * 4, hipMemcpyHostToDevice, s->stream));
       std::vector<int> zeros(g.n_wg + 1, 0);
       s->src_ptr.alloc(g.n_wg + 1);
       s->rec_ptr.alloc(g.n_wg + 1);
@@ -371,7 +371,7 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
     const size_t ne = s->n_elem;
     const int64_t nx = s->nx, ny = s->ny, nz = s->nz;
     const double h = s->h;
-    std::vector<double> ls(ne), ms(ne), mass(s->n_nodes, 0.0);
+    std::vector<double> mt(2 * ne), mass(s->n_nodes, 0.0);
     // stability: largest eigenvalues of the two reference matrices
     std::vector<double> al(576), am(576);
     for (int i = 0; i < 24; ++i)
@@ -387,7 +387,7 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
           const size_t e = (size_t)(i + nx * (j + ny * k));
           const bool sol = solid == nullptr || solid[e] != 0;
           if (!sol) {
-            ls[e] = ms[e] = 0.0;
+            mt[2 * e] = mt[2 * e + 1] = 0.0;
             continue;
           }
           const double L = lam[e], M = mu[e], R = rho[e];
@@ -395,8 +395,8 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
                   "ovfem_set_model: non-finite material in element " + std::to_string(e));
           require(M > 0 && L + 2.0 * M / 3.0 > 0 && R > 0,
                   "ovfem_set_model: need mu > 0, lam + 2 mu / 3 > 0, rho > 0 (element " + std::to_string(e) + ")");
-          ls[e] = h * L / 256.0;
-          ms[e] = h * M / 128.0;
+          mt[2 * e] = h * L / 256.0;
+          mt[2 * e + 1] = h * M / 128.0;
           const double me = R * h * h * h / 8.0;
           // lambda_max(lam K_lam + mu K_mu) <= max(lam, 0) lambda_max(K_lam) + mu lambda_max(K_mu)
           wmax2 = std::max(wmax2, h * (std::max(L, 0.0) * el + M * em) / me);
@@ -406,8 +406,7 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
                 mass[(size_t)((i + di) + (nx + 1) * ((j + dj) + (ny + 1) * (k + dk)))] += me;
         }
     s->dt_bound = wmax2 > 0 ? 2.0 / std::sqrt(wmax2) : std::numeric_limits<double>::infinity();
-    OVFEM_HIP(hipMemcpyAsync(s->lam_s.p, ls.data(), ne * sizeof(double), hipMemcpyHostToDevice, s->stream));
-    OVFEM_HIP(hipMemcpyAsync(s->mu_s.p, ms.data(), ne * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    OVFEM_HIP(hipMemcpyAsync(s->mat.p, mt.data(), 2 * ne * sizeof(double), hipMemcpyHostToDevice, s->stream));
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     s->mass.swap(mass);
     s->model_set = true;
