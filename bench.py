@@ -16,6 +16,7 @@ of the same workload on the host's cores.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,9 +30,55 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF-updates/s/step: INT8-MFMA vs FP64 path at ≤1e-9 trace rel err; % roofline"
 HBM_PEAK = 8.0e12          # bytes/s
 INT8_PEAK = 5.0e15         # dense INT8 MFMA ops/s
+BF16_PEAK = 2.5e15         # dense bf16 MFMA flop/s (the digit products run on bf16 matrix cores)
 FP64_PEAK = 78.6e12        # FP64 vector flop/s
 INT8_OPS_PER_ELEMENT = 2 * 48 * 24 * 8    # [AL; AM] (48 x 24) times 8 digit slices
 FP64_FLOP_PER_ELEMENT = 2 * 2 * 24 * 24   # AL u and AM u in FP64
+
+
+KERNEL_SOURCES = ["paper_2404_13683_amd/csrc/kernels.hpp", "paper_2404_13683_amd/csrc/refmat.hpp"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "layer_kernel_counters_layered_256x256x128.txt")
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor)."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    kv = {}
+    for line in open(COUNTERS_FILE):
+        line = line.strip()
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    try:
+        f = float(kv["%s_fetch_kib" % path_name]) * float(kv["fetch_factor"])
+        w = float(kv["%s_write_kib" % path_name]) * float(kv["write_factor"])
+    except KeyError:
+        return None
+    return (f + w) * 1024.0
+
+
+def copy_probe(nbytes):
+    """A plain copy of a known size (float32 elementwise kernel: nbytes read, nbytes written),
+    used to calibrate the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.add(src, 0.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
 def algorithmic_bytes(nx, ny, nz):
@@ -93,7 +140,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--paths", default="fp64,int8")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
               "sharding is described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
@@ -127,19 +178,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8-mfma+f64" if head == "int8" else "f64",
+        "dtype": "int8-digits(bf16-mfma,exact)+f64" if head == "int8" else "f64",
         "data": "synthetic",
         "config": {"workload": "layered-256x256x128 (8.4M voxels, %d free DOF), h=5 m, Ricker 5 Hz, dt=%.4e s"
                                % (free_dof, wl.dt),
                    "path": head, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz},
         "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": hbm / HBM_PEAK, "traffic": None,
+                     "frac": hbm / HBM_PEAK, "traffic": measured_traffic(head), "kernel_sha": kernel_sha(),
                      "algorithmic_bytes_per_step": bytes_step,
-                     "mfma_frac": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / INT8_PEAK if head == "int8" else None},
+                     "mfma_frac_int8_peak": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / INT8_PEAK
+                     if head == "int8" else None,
+                     "mfma_frac_bf16_peak": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / BF16_PEAK
+                     if head == "int8" else None},
     }
     if "fp64" in res:
         f = res["fp64"]
-        out["fp64_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"],
+        out["fp64_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"], "traffic": measured_traffic("fp64"),
                             "fp64_frac": FP64_FLOP_PER_ELEMENT * n_elem / (f["ms_per_step"] * 1e-3) / FP64_PEAK,
                             "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK}
     if "fp64" in res and "int8" in res:
