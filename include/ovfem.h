@@ -12,11 +12,15 @@
  *     (Sec. 2, Eqs. (3) and (6)):
  *         u^{n+1} = 2 u^n - u^{n-1} + dt^2 M^{-1} (F^n - K u^n),
  *     fixed DOFs held at zero;
- *   - in two precisions: OVFEM_FP64 evaluates the element products in FP64; OVFEM_INT8
- *     splits u into INT8 digit slices under a per-tile power-of-two exponent, runs the
- *     products on INT8 matrix cores with INT32 accumulation and recombines the slices
- *     exactly into FP64 (Sec. 2, Eqs. (10)-(17), hierarchical FP64-INT64-INT8 form);
- *     everything outside the INT8 products is FP64 (Sec. 3).
+ *   - in two precisions: OVFEM_FP64 evaluates the element products in FP64; the INT8
+ *     forms split u into M = 8 INT8 digit slices of a 62-bit fixed-point value under a
+ *     per-tile power-of-two exponent, run the digit products on the matrix cores and
+ *     recombine them into FP64 (Sec. 2, Eqs. (10)-(17), hierarchical FP64-INT64-INT8
+ *     form); everything outside the digit products is FP64 (Sec. 3).  Two matrix-core
+ *     forms give identical digit products: OVFEM_INT8 accumulates two digits per FP32
+ *     accumulator on bf16 matrix cores (every operand and partial sum is an integer
+ *     that bf16/FP32 represent exactly), OVFEM_INT8_I32 runs int8 matrix cores with
+ *     INT32 accumulation.
  *
  * Grid layout (shared by every array argument):
  *   elements e = i + nx (j + ny k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
@@ -53,7 +57,8 @@ typedef int32_t ovfem_status;
 
 /* precision of the element products */
 #define OVFEM_FP64 0
-#define OVFEM_INT8 1
+#define OVFEM_INT8 1     /* INT8 digit slices, bf16 matrix cores, exact FP32 digit-pair sums */
+#define OVFEM_INT8_I32 2 /* INT8 digit slices, int8 matrix cores, INT32 accumulation */
 
 typedef struct ovfem_solver ovfem_solver;
 
@@ -65,8 +70,9 @@ int32_t ovfem_version(void);
 const char* ovfem_last_error(void);
 
 /* Create a solver for an nx x ny x nz voxel grid of edge h (> 0) on the current HIP
- * device.  n_shots must be 1.  precision is OVFEM_FP64 or OVFEM_INT8.  stream is a
+ * device.  n_shots must be 1.  stream is a
  * hipStream_t (NULL = the legacy default stream); all work is enqueued on it.
+ * precision is OVFEM_FP64, OVFEM_INT8 or OVFEM_INT8_I32.
  * EINVAL for non-positive sizes, h <= 0, unknown precision; ENOMEM if the device
  * buffers do not fit. */
 ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz, double h,
@@ -75,7 +81,7 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
 /* Free every device buffer of the solver (waits for its stream).  NULL is accepted. */
 ovfem_status ovfem_destroy(ovfem_solver* s);
 
-/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8). */
+/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_I32). */
 ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision);
 
 /* Per-element material, HOST arrays of nx*ny*nz float64: Lame lam, shear modulus mu,
@@ -137,6 +143,31 @@ ovfem_status ovfem_get_traces(ovfem_solver* s, double* out);
 
 /* Current step counter (number of steps taken since reset / set_wavefield). */
 ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step);
+
+/* Checkpointing of forward runs for ovfem_adjoint: allocates room for max_steps steps
+ * and, from now on, stores (u^s, u^{s-1}) on the device at every step s that is a
+ * multiple of `every` (counted from reset).  every = 0 disables it.  Resets the
+ * wavefield (as ovfem_reset).  Device memory: 2 (max_steps / every + 1) nodal vectors.
+ * ENOMEM if it does not fit. */
+ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max_steps);
+
+/* Gradient of a receiver misfit with respect to the per-element lam and mu, by the
+ * discrete adjoint of the central-difference recursion (Sec. 2, Eq. (3)).  With
+ * A = dt^2 M^{-1} (zero on fixed DOFs), R the receiver restriction and r^n = dJ/d(traces
+ * at step n), the adjoint states obey
+ *     w^{N+1} = w^{N+2} = 0,   w^m = 2 w^{m+1} - w^{m+2} + A (R^T r^{m-1} - K w^{m+1}),
+ * which is the forward step with the residual injected at the receivers, and
+ *     g_lam[e] = - sum_m h (w_e^m)^T K_lam u_e^{m-1}   (g_mu likewise with K_mu).
+ * Requires a forward run of N >= 1 steps from reset with checkpointing enabled, the same
+ * precision, model and dt, and receivers recording every step (N <= nt_max).
+ * residual: DEVICE float64 [receiver][component][nt_max] (the layout of the traces;
+ * entries t >= N are ignored), e.g. traces - observed for J = 1/2 |traces - observed|^2.
+ * g_lam, g_mu: DEVICE float64 arrays of nx*ny*nz, overwritten (0 for removed voxels).
+ * Each checkpoint segment is recomputed forward (bitwise identical: the kernels are
+ * deterministic) and then stepped backward; the adjoint steps use the solver's
+ * precision for K.  The wavefield state and traces of the forward run are unchanged.
+ * Synchronises the stream.  ESTATE if the preconditions do not hold. */
+ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_lam, double* g_mu);
 
 /* Wait for all work enqueued by the solver. */
 ovfem_status ovfem_synchronize(ovfem_solver* s);

@@ -52,19 +52,27 @@ constexpr int NODE_DW = 16;   // dwords of one staged node: 4 pairs x (hi, lo) x
 // lane (its element's nodes x and x+1 in one row) is 16 contiguous bytes
 constexpr int DPLANE = PN * PN * NODE_DW;  // dwords per staged digit plane
 constexpr int DROW = NPAIR * 2 * PN * 2;   // dwords per staged digit row
+// i8 form: [row q][digit j][column x] one dword (c0, c1, c2, 0) of signed digits
+constexpr int NDIG = 2 * NPAIR;
+constexpr int DROW8 = NDIG * PN;
+constexpr int DPLANE8 = PN * DROW8;
 constexpr int FPLANE = 3 * PN * PN;        // doubles per staged FP64 plane
 constexpr int NEXTRA = PN * PN - NTHR;     // staged nodes beyond one per thread (33)
 constexpr int EXP_NONE = -1000000;         // exponent of an all-zero tile
 
 static_assert(kMaxRowAbs * 128 * 256 + kMaxRowAbs * 255 < (1 << 24),
               "digit-pair sums must be exact in FP32");
+static_assert((long long)kMaxRowAbs * 128 * 257 < 2147483647LL, "digit-pair sums must fit INT32");
 
 enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
-enum : int { PATH_FP64 = 0, PATH_INT8 = 1 };
+// PATH_INT8: digit pairs on bf16 matrix cores, exact FP32 accumulation;
+// PATH_I8: digits on i8 matrix cores, INT32 accumulation with a shift per pair.
+enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_I8 = 2 };
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 struct Geom {
   int nx, ny, nz;  // elements per axis
@@ -76,13 +84,16 @@ struct Geom {
 struct KArgs {
   Geom g;
   const double* u;        // u^n, [node][3]
-  double* uprev_next;     // in: u^{n-1}; out: u^{n+1} (same array)
+  const double* uprev;    // u^{n-1}
+  double* unext;          // u^{n+1}; may be the same array as uprev (each node is read
+                          // and then written by one thread)
   double* ku;             // MODE_MATVEC output K u, [node][3]
   const double* mat;      // [element][2] = (h lam / 256, h mu / 128), 0 for removed voxels
   const double* acoef;    // dt^2 / m per node, 0 where the node does not move
   const int* exp_in;      // per tile: exponent e with max |u^n| < 2^e (INT8 path)
   int* exp_out;           // per tile: same for u^{n+1} (MODE_STEP)
   const v4u* alane;       // INT8 A operands, [3 row tiles][64 lanes] x 8 bf16
+  const uint64_t* alane8; // I8 A operands, [3 row tiles][64 lanes] x 8 int8
   const int* src_ptr;     // [n_wg + 1] CSR of sources per tile
   const int* src_node;    // node id of each listed source
   const int* src_comp;    // component
@@ -201,6 +212,30 @@ __device__ inline void stage_digits(const D3& u, int E, uint32_t* dst) {
     }
 }
 
+// i8 form of the node staging: per digit j the word (d_j(c0), d_j(c1), d_j(c2), 0) of
+// signed digits, written at dst[j * PN] (dst = the node's column in its row).
+__device__ inline void stage_digits_i8(const D3& u, int E, uint32_t* dst) {
+  uint32_t lo[3], hi[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double x = ldexp(u.v[c], QBITS - E);
+    const double hd = floor(x * 0x1p-32);
+    const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);
+    const uint64_t q = ((uint64_t)(uint32_t)(int)hd << 32) | lo_u;
+    const uint64_t d = q + 0x8080808080808080ull;  // bytes d_j + 128
+    lo[c] = (uint32_t)d ^ 0x80808080u;              // bytes d_j (two's complement)
+    hi[c] = (uint32_t)(d >> 32) ^ 0x80808080u;
+  }
+#pragma unroll
+  for (int j = 0; j < NDIG; ++j) {
+    const uint32_t* s = j < 4 ? lo : hi;
+    const int sel = j & 3;
+    // bytes: c0 byte sel, c1 byte sel, c2 byte sel, 0
+    const uint32_t t01 = __builtin_amdgcn_perm(s[1], s[0], 0x0c0c0400u | (sel << 8) | sel);
+    dst[j * PN] = __builtin_amdgcn_perm(s[2], t01, 0x0c040100u | (sel << 16));
+  }
+}
+
 // Per-element FP64 product: y = lam_s AL ue + mu_s AM ue.
 __device__ inline void element_fp64(const double ue[24], double lam_s, double mu_s, double y[24]) {
 #pragma unroll
@@ -251,7 +286,7 @@ __device__ inline void write_tile_exponent(double local_max, int* dst, double* r
 }
 
 template <int PATH, int MODE>
-__global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_kernel(KArgs A) {
+__global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_kernel(KArgs A) {
   const Geom g = A.g;
   const int wg = logical_tile(blockIdx.x, g.n_wg);
   const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
@@ -264,15 +299,15 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
   __shared__ double lsum[TE * 3 * TE];  // [q][c][p], q = 0..15
   __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
   __shared__ double red[4];
-  __shared__ __attribute__((aligned(16))) double matl[PATH == PATH_INT8 ? 2 * NTHR : 2];  // INT8: [b][a] material
-  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : 2 * DPLANE * 4;
+  __shared__ __attribute__((aligned(16))) double matl[PATH == PATH_FP64 ? 2 : 2 * NTHR];  // slices: [b][a] material
+  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : (PATH == PATH_INT8 ? 2 * DPLANE * 4 : 2 * DPLANE8 * 4);
   __shared__ __attribute__((aligned(16))) unsigned char ring_raw[RING_BYTES];
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
 
   // ---- tile exponent (INT8): max over the 27 tiles owning the staged nodes
   int E = 0;
-  if (PATH == PATH_INT8) {
+  if (PATH != PATH_FP64) {
     int e = EXP_NONE;
     for (int dz = -1; dz <= 1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
@@ -284,9 +319,14 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
     E = e == EXP_NONE ? 0 : e;
   }
   v8bf a_frag[3];
+  long a_frag8[3];
   if (PATH == PATH_INT8) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) a_frag[i] = __builtin_bit_cast(v8bf, A.alane[i * 64 + lane]);
+  }
+  if (PATH == PATH_I8) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a_frag8[i] = (long)A.alane8[i * 64 + lane];
   }
 
   // staged nodes: main node (ta+1, tb+1); the first 33 lanes of the last wave stage
@@ -338,10 +378,14 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
       if (has_extra)
 #pragma unroll
         for (int c = 0; c < 3; ++c) P[(c * PN + xq) * PN + xp] = u_extra_next.v[c];
-    } else {
+    } else if (PATH == PATH_INT8) {
       uint32_t* P = ringd + slot * DPLANE;
       stage_digits(u_main_next, E, P + mq * DROW + 2 * mp);
       if (has_extra) stage_digits(u_extra_next, E, P + xq * DROW + 2 * xp);
+    } else {
+      uint32_t* P = ringd + slot * DPLANE8;
+      stage_digits_i8(u_main_next, E, P + mq * DROW8 + mp);
+      if (has_extra) stage_digits_i8(u_extra_next, E, P + xq * DROW8 + xp);
     }
   };
 
@@ -357,7 +401,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
     u_own_top = u_main_next;
     stage(top);
     const double2 mat_e = mat_next;
-    if (PATH == PATH_INT8) {
+    if (PATH != PATH_FP64) {
       matl[2 * t] = mat_e.x;
       matl[2 * t + 1] = mat_e.y;
     }
@@ -369,7 +413,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
     const size_t node_off = (size_t)k * plane_bytes + main_ref.off;  // byte offset of owned node
     double up[3] = {0.0, 0.0, 0.0}, ac = 0.0;
     if (do_node && MODE == MODE_STEP) {
-      const double* pp = reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.uprev_next) + node_off);
+      const double* pp = reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.uprev) + node_off);
       up[0] = pp[0];
       up[1] = pp[1];
       up[2] = pp[2];
@@ -409,41 +453,70 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
       for (int i = 0; i < 12; ++i) top_f[i] = y[12 + i];
     } else {
       const int ja = lane & 15, G = lane >> 4;  // element column; lane group
-      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * DPLANE;
+      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_INT8 ? DPLANE : DPLANE8);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int b = 4 * wave + tt;
         double ybot[3] = {0.0, 0.0, 0.0}, ytop[3] = {0.0, 0.0, 0.0};
         if (layer_ok) {
           const double2 me = *reinterpret_cast<const double2*>(matl + 2 * (b * TE + ja));
-          const uint32_t* P = Pin + (b + (G & 1)) * DROW + 2 * ja;
           double R[12];
 #pragma unroll
           for (int p = NPAIR - 1; p >= 0; --p) {
-            // the lane's eight K slots: (c0, c1, c2, 0) of node ja, then of node ja+1
-            const uint2* ph = reinterpret_cast<const uint2*>(P + (2 * p) * PN * 2);
-            const uint2* pl = reinterpret_cast<const uint2*>(P + (2 * p + 1) * PN * 2);
-            const uint2 h0 = ph[0], h1 = ph[1], l0 = pl[0], l1 = pl[1];
-            const v4u bh = {h0.x, h0.y, h1.x, h1.y};
-            const v4u bl = {l0.x, l0.y, l1.x, l1.y};
-            const v8bf Bh = __builtin_bit_cast(v8bf, bh), Bl = __builtin_bit_cast(v8bf, bl);
-            const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
-            v4f c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[0], Bh, z, 0, 0, 0);
-            v4f c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[1], Bh, z, 0, 0, 0);
-            v4f c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bh, z, 0, 0, 0);
-            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[0], Bl, c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[1], Bl, c1, 0, 0, 0);
-            c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bl, c2, 0, 0, 0);
+            if constexpr (PATH == PATH_INT8) {
+              // the lane's eight K slots: (c0, c1, c2, 0) of node ja, then of node ja+1
+              const uint32_t* P = Pin + (b + (G & 1)) * DROW + 2 * ja;
+              const uint2* ph = reinterpret_cast<const uint2*>(P + (2 * p) * PN * 2);
+              const uint2* pl = reinterpret_cast<const uint2*>(P + (2 * p + 1) * PN * 2);
+              const uint2 h0 = ph[0], h1 = ph[1], l0 = pl[0], l1 = pl[1];
+              const v4u bh = {h0.x, h0.y, h1.x, h1.y};
+              const v4u bl = {l0.x, l0.y, l1.x, l1.y};
+              const v8bf Bh = __builtin_bit_cast(v8bf, bh), Bl = __builtin_bit_cast(v8bf, bl);
+              const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+              v4f c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[0], Bh, z, 0, 0, 0);
+              v4f c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[1], Bh, z, 0, 0, 0);
+              v4f c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bh, z, 0, 0, 0);
+              c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[0], Bl, c0, 0, 0, 0);
+              c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[1], Bl, c1, 0, 0, 0);
+              c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bl, c2, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              if (p == NPAIR - 1) {
-                R[r] = (double)c0[r];
-                R[4 + r] = (double)c1[r];
-                R[8 + r] = (double)c2[r];
-              } else {
-                R[r] = fma(R[r], 65536.0, (double)c0[r]);
-                R[4 + r] = fma(R[4 + r], 65536.0, (double)c1[r]);
-                R[8 + r] = fma(R[8 + r], 65536.0, (double)c2[r]);
+              for (int r = 0; r < 4; ++r) {
+                if (p == NPAIR - 1) {
+                  R[r] = (double)c0[r];
+                  R[4 + r] = (double)c1[r];
+                  R[8 + r] = (double)c2[r];
+                } else {
+                  R[r] = fma(R[r], 65536.0, (double)c0[r]);
+                  R[4 + r] = fma(R[4 + r], 65536.0, (double)c1[r]);
+                  R[8 + r] = fma(R[8 + r], 65536.0, (double)c2[r]);
+                }
+              }
+            } else {
+              // digit words of node ja and ja+1 for digits 2p+1 (hi) and 2p (lo)
+              const uint32_t* P = Pin + (b + (G & 1)) * DROW8 + ja;
+              const long Bh = (long)((uint64_t)P[(2 * p + 1) * PN] | ((uint64_t)P[(2 * p + 1) * PN + 1] << 32));
+              const long Bl = (long)((uint64_t)P[(2 * p) * PN] | ((uint64_t)P[(2 * p) * PN + 1] << 32));
+              const v4i z = {0, 0, 0, 0};
+              v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[0], Bh, z, 0, 0, 0);
+              v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[1], Bh, z, 0, 0, 0);
+              v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[2], Bh, z, 0, 0, 0);
+              c0 = c0 << 8;
+              c1 = c1 << 8;
+              c2 = c2 << 8;
+              c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[0], Bl, c0, 0, 0, 0);
+              c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[1], Bl, c1, 0, 0, 0);
+              c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[2], Bl, c2, 0, 0, 0);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                if (p == NPAIR - 1) {
+                  R[r] = (double)c0[r];
+                  R[4 + r] = (double)c1[r];
+                  R[8 + r] = (double)c2[r];
+                } else {
+                  R[r] = fma(R[r], 65536.0, (double)c0[r]);
+                  R[4 + r] = fma(R[4 + r], 65536.0, (double)c1[r]);
+                  R[8 + r] = fma(R[8 + r], 65536.0, (double)c2[r]);
+                }
               }
             }
           }
@@ -506,7 +579,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_INT8 ? 2 : 1) ovfem_layer_k
 #pragma unroll
         for (int c = 0; c < 3; ++c)
           un[c] = ac > 0.0 ? 2.0 * u_own_bot.v[c] - up[c] + ac * (F[c] - f[c]) : 0.0;
-        double* o = A.uprev_next + 3 * nid;
+        double* o = A.unext + 3 * nid;
         o[0] = un[0];
         o[1] = un[1];
         o[2] = un[2];
@@ -539,6 +612,47 @@ __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const doub
       m = fmax(m, fmax(fabs(p[0]), fmax(fabs(p[1]), fabs(p[2]))));
     }
   write_tile_exponent(m, exp_out + wg, red);
+}
+
+// Per-element gradient terms of the discrete adjoint: for every solid element e,
+//     g_lam[e] -= h w_e^T K_lam u_e,   g_mu[e] -= h w_e^T K_mu u_e,
+// with u = u^{m-1} and w = w^m (the derivative of w^T K u with respect to lam_e, mu_e,
+// from K_e = h (lam_e K_lam + mu_e K_mu)).  One thread per element; each element's
+// sums are private, so the accumulation order is fixed.
+__global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, const double* mat,
+                                                               const double* u, const double* w,
+                                                               double* g_lam, double* g_mu) {
+  const long long e = (long long)blockIdx.x * NTHR + threadIdx.x;
+  const long long ne = (long long)g.nx * g.ny * g.nz;
+  if (e >= ne) return;
+  const double2 m = reinterpret_cast<const double2*>(mat)[e];
+  if (m.x == 0.0 && m.y == 0.0) return;  // removed voxel
+  const int X = (int)(e % g.nx), Y = (int)((e / g.nx) % g.ny), Z = (int)(e / ((long long)g.nx * g.ny));
+  double ue[24], we[24];
+#pragma unroll
+  for (int alpha = 0; alpha < 8; ++alpha) {
+    const long long n = (long long)(X + (alpha & 1)) +
+                        (long long)(g.nx + 1) * ((Y + ((alpha >> 1) & 1)) + (long long)(g.ny + 1) * (Z + (alpha >> 2)));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      ue[3 * alpha + c] = u[3 * n + c];
+      we[3 * alpha + c] = w[3 * n + c];
+    }
+  }
+  double gl = 0.0, gm = 0.0;
+#pragma unroll
+  for (int r = 0; r < 24; ++r) {
+    double sl = 0.0, sm = 0.0;
+#pragma unroll
+    for (int q = 0; q < 24; ++q) {
+      sl = fma((double)kRef.AL[r][q], ue[q], sl);
+      sm = fma((double)kRef.AM[r][q], ue[q], sm);
+    }
+    gl = fma(we[r], sl, gl);
+    gm = fma(we[r], sm, gm);
+  }
+  g_lam[e] -= h / 256.0 * gl;
+  g_mu[e] -= h / 128.0 * gm;
 }
 
 }  // namespace ovfem

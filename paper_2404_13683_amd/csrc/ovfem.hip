@@ -130,6 +130,27 @@ std::vector<uint32_t> make_alane() {
   return out;
 }
 
+// I8 A fragments: the same matrix entries as make_alane(), as int8 bytes.
+std::vector<uint64_t> make_alane8() {
+  std::vector<uint64_t> out(3 * 64, 0);
+  for (int t = 0; t < 3; ++t)
+    for (int l = 0; l < 64; ++l) {
+      const int i = l % 16, kg = l / 16;
+      const int G = i / 4, s = 4 * t + i % 4;
+      const int which = s / 6, dk = (s % 6) / 3, c = s % 3;
+      const int m = 3 * (G + 4 * dk) + c;
+      for (int q = 0; q < 8; ++q) {
+        const int k = 8 * kg + q, node = k / 4, cp = k % 4;
+        int v = 0;
+        if (cp < 3) v = which == 0 ? kRef.AL[m][3 * node + cp] : kRef.AM[m][3 * node + cp];
+        out[t * 64 + l] |= (uint64_t)(uint8_t)(int8_t)v << (8 * q);
+      }
+    }
+  return out;
+}
+
+bool valid_precision(int p) { return p == OVFEM_FP64 || p == OVFEM_INT8 || p == OVFEM_INT8_I32; }
+
 }  // namespace
 
 struct ovfem_solver {
@@ -149,6 +170,7 @@ struct ovfem_solver {
   int exp_cur = 0;
   bool exp_valid = false;
   DevBuf<uint32_t> alane;
+  DevBuf<uint64_t> alane8;
 
   DevBuf<int> src_ptr, src_node, src_comp, src_row;
   DevBuf<double> wavelet;
@@ -156,6 +178,12 @@ struct ovfem_solver {
   DevBuf<int> rec_ptr, rec_node, rec_idx;
   DevBuf<double> traces;
   int rec_nt = 0, n_rec = 0;
+
+  // adjoint: forward checkpoints (u^s, u^{s-1}) at s = 0, every, 2 every, ... since reset
+  int64_t ckpt_every = 0, ckpt_slots = 0;
+  DevBuf<double> ckpt;           // [slot][2][3 n_nodes]
+  bool ckpt_valid = false;       // the run since reset was checkpointed with this precision
+  int ckpt_precision = OVFEM_FP64;
 
   std::vector<double> mass;      // nodal mass (host)
   std::vector<uint8_t> fixed;    // nodal fixed flags (host)
@@ -173,6 +201,7 @@ struct ovfem_solver {
     expo[1].free();
     expo_tmp.free();
     alane.free();
+    alane8.free();
     src_ptr.free();
     src_node.free();
     src_comp.free();
@@ -182,7 +211,10 @@ struct ovfem_solver {
     rec_node.free();
     rec_idx.free();
     traces.free();
+    ckpt.free();
   }
+
+  double* ckpt_u(int64_t slot, int which) { return ckpt.p + (size_t)(2 * slot + which) * 3 * n_nodes; }
 
   int tile_of(int64_t X, int64_t Y, int64_t Z) const {
     return (int)(X / TN + geom.tiles_x * (Y / TN + geom.tiles_y * (Z / geom.tz)));
@@ -215,6 +247,7 @@ struct ovfem_solver {
     A.mat = mat.p;
     A.acoef = acoef.p;
     A.alane = reinterpret_cast<const v4u*>(alane.p);
+    A.alane8 = alane8.p;
     A.src_ptr = src_ptr.p;
     A.src_node = src_node.p;
     A.src_comp = src_comp.p;
@@ -236,11 +269,16 @@ struct ovfem_solver {
         ovfem_layer_kernel<PATH_FP64, MODE_STEP><<<grid, block, 0, stream>>>(A);
       else
         ovfem_layer_kernel<PATH_FP64, MODE_MATVEC><<<grid, block, 0, stream>>>(A);
-    } else {
+    } else if (precision == OVFEM_INT8) {
       if (mode == MODE_STEP)
         ovfem_layer_kernel<PATH_INT8, MODE_STEP><<<grid, block, 0, stream>>>(A);
       else
         ovfem_layer_kernel<PATH_INT8, MODE_MATVEC><<<grid, block, 0, stream>>>(A);
+    } else {
+      if (mode == MODE_STEP)
+        ovfem_layer_kernel<PATH_I8, MODE_STEP><<<grid, block, 0, stream>>>(A);
+      else
+        ovfem_layer_kernel<PATH_I8, MODE_MATVEC><<<grid, block, 0, stream>>>(A);
     }
     OVFEM_HIP(hipGetLastError());
   }
@@ -253,6 +291,8 @@ struct ovfem_solver {
     step = 0;
     launch_exponents(u[cur].p, expo[exp_cur].p);
     exp_valid = true;
+    ckpt_valid = ckpt_every > 0;
+    ckpt_precision = precision;
   }
 
   void do_steps(int64_t n) {
@@ -264,9 +304,21 @@ struct ovfem_solver {
       exp_valid = true;
     }
     KArgs A = base_args();
+    if (ckpt_valid && precision != ckpt_precision) ckpt_valid = false;
     for (int64_t i = 0; i < n; ++i) {
+      if (ckpt_valid && step % ckpt_every == 0) {
+        const int64_t slot = step / ckpt_every;
+        if (slot < ckpt_slots) {
+          const size_t bytes = 3 * n_nodes * sizeof(double);
+          OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 0), u[cur].p, bytes, hipMemcpyDeviceToDevice, stream));
+          OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 1), u[cur ^ 1].p, bytes, hipMemcpyDeviceToDevice, stream));
+        } else {
+          ckpt_valid = false;  // ran past the checkpoint capacity
+        }
+      }
       A.u = u[cur].p;
-      A.uprev_next = u[cur ^ 1].p;
+      A.uprev = u[cur ^ 1].p;
+      A.unext = u[cur ^ 1].p;
       A.exp_in = expo[exp_cur].p;
       A.exp_out = expo[exp_cur ^ 1].p;
       A.step = step;
@@ -292,7 +344,7 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
     require(nx > 0 && ny > 0 && nz > 0, "ovfem_create: grid sizes must be positive");
     require(std::isfinite(h) && h > 0, "ovfem_create: h must be positive");
     require(n_shots == 1, "ovfem_create: n_shots must be 1");
-    require(precision == OVFEM_FP64 || precision == OVFEM_INT8, "ovfem_create: unknown precision");
+    require(valid_precision(precision), "ovfem_create: unknown precision");
     const double nn = double(nx + 1) * double(ny + 1) * double(nz + 1);
     require(nn < 2147483647.0, "ovfem_create: more than 2^31 - 1 nodes");
     auto s = new ovfem_solver();
@@ -326,6 +378,9 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
       auto al = make_alane();
       s->alane.alloc(al.size());
       OVFEM_HIP(hipMemcpyAsync(s->alane.p, al.data(), al.size() * 4, hipMemcpyHostToDevice, s->stream));
+      auto al8 = make_alane8();
+      s->alane8.alloc(al8.size());
+      OVFEM_HIP(hipMemcpyAsync(s->alane8.p, al8.data(), al8.size() * 8, hipMemcpyHostToDevice, s->stream));
       std::vector<int> zeros(g.n_wg + 1, 0);
       s->src_ptr.alloc(g.n_wg + 1);
       s->rec_ptr.alloc(g.n_wg + 1);
@@ -357,7 +412,7 @@ ovfem_status ovfem_destroy(ovfem_solver* s) {
 ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_precision: solver is NULL");
-    require(precision == OVFEM_FP64 || precision == OVFEM_INT8, "ovfem_set_precision: unknown precision");
+    require(valid_precision(precision), "ovfem_set_precision: unknown precision");
     s->precision = precision;
   });
 }
@@ -573,7 +628,7 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
     KArgs A = s->base_args();
     A.u = u;
     A.ku = Ku;
-    if (s->precision == OVFEM_INT8) {
+    if (s->precision != OVFEM_FP64) {
       s->launch_exponents(u, s->expo_tmp.p);
       A.exp_in = s->expo_tmp.p;
     }
@@ -604,6 +659,7 @@ ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double
     s->launch_exponents(s->u[s->cur].p, s->expo[s->exp_cur].p);
     s->exp_valid = true;
     s->step = step;
+    s->ckpt_valid = false;
     OVFEM_HIP(hipStreamSynchronize(s->stream));
   });
 }
@@ -623,6 +679,143 @@ ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step) {
   return guarded([&] {
     require(s != nullptr && step != nullptr, "ovfem_get_step: NULL argument");
     *step = s->step;
+  });
+}
+
+ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max_steps) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_set_checkpointing: solver is NULL");
+    require(every >= 0 && max_steps >= 0, "ovfem_set_checkpointing: negative argument");
+    s->check_device();
+    DevBuf<double> buf;
+    int64_t slots = 0;
+    if (every > 0) {
+      slots = max_steps / every + 1;
+      buf.alloc((size_t)slots * 2 * 3 * s->n_nodes);
+    }
+    OVFEM_HIP(hipStreamSynchronize(s->stream));
+    std::swap(s->ckpt, buf);
+    buf.free();
+    s->ckpt_every = every;
+    s->ckpt_slots = slots;
+    s->zero_state();
+    OVFEM_HIP(hipStreamSynchronize(s->stream));
+  });
+}
+
+ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_lam, double* g_mu) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_adjoint: solver is NULL");
+    require(residual && g_lam && g_mu, "ovfem_adjoint: NULL array");
+    s->check_device();
+    const int64_t n = s->step;
+    require(s->ckpt_valid && s->ckpt_every > 0,
+            "ovfem_adjoint: the forward run since reset was not checkpointed (call ovfem_set_checkpointing, "
+            "then step from reset without changing precision or wavefield)", OVFEM_ESTATE);
+    require(n >= 1, "ovfem_adjoint: no forward steps to differentiate", OVFEM_ESTATE);
+    require(s->n_rec > 0 && n <= s->rec_nt, "ovfem_adjoint: receivers must record every forward step", OVFEM_ESTATE);
+    require(s->model_set && s->dt_set, "ovfem_adjoint: model and dt not set", OVFEM_ESTATE);
+    s->refresh_acoef();
+    const int64_t every = s->ckpt_every;
+    const size_t vec = 3 * s->n_nodes;
+    const Geom& g = s->geom;
+
+    // adjoint sources: every receiver component, with the residual as its force
+    std::vector<int> rec_node_h(s->n_rec), rec_idx_h(s->n_rec), rec_ptr_h(g.n_wg + 1);
+    OVFEM_HIP(hipMemcpy(rec_node_h.data(), s->rec_node.p, s->n_rec * 4, hipMemcpyDeviceToHost));
+    OVFEM_HIP(hipMemcpy(rec_idx_h.data(), s->rec_idx.p, s->n_rec * 4, hipMemcpyDeviceToHost));
+    OVFEM_HIP(hipMemcpy(rec_ptr_h.data(), s->rec_ptr.p, (g.n_wg + 1) * 4, hipMemcpyDeviceToHost));
+    std::vector<int> aptr(g.n_wg + 1, 0), anode, acomp, arow;
+    for (int w = 0; w < g.n_wg; ++w) {
+      for (int r = rec_ptr_h[w]; r < rec_ptr_h[w + 1]; ++r)
+        for (int c = 0; c < 3; ++c) {
+          anode.push_back(rec_node_h[r]);
+          acomp.push_back(c);
+          arow.push_back(3 * rec_idx_h[r] + c);
+        }
+      aptr[w + 1] = (int)anode.size();
+    }
+    DevBuf<int> d_aptr, d_anode, d_acomp, d_arow;
+    DevBuf<double> seg, wbuf, zeros;
+    DevBuf<int> fexp, wexp;
+    d_aptr.alloc(aptr.size());
+    d_anode.alloc(anode.size());
+    d_acomp.alloc(acomp.size());
+    d_arow.alloc(arow.size());
+    seg.alloc((size_t)(every + 1) * vec);
+    wbuf.alloc(2 * vec);
+    fexp.alloc(2 * g.n_wg);
+    wexp.alloc(2 * g.n_wg);
+    auto free_all = [&] {
+      d_aptr.free(); d_anode.free(); d_acomp.free(); d_arow.free();
+      seg.free(); wbuf.free(); fexp.free(); wexp.free();
+    };
+    try {
+      OVFEM_HIP(hipMemcpyAsync(d_aptr.p, aptr.data(), aptr.size() * 4, hipMemcpyHostToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(d_anode.p, anode.data(), anode.size() * 4, hipMemcpyHostToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(d_acomp.p, acomp.data(), acomp.size() * 4, hipMemcpyHostToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(d_arow.p, arow.data(), arow.size() * 4, hipMemcpyHostToDevice, s->stream));
+      OVFEM_HIP(hipMemsetAsync(g_lam, 0, s->n_elem * sizeof(double), s->stream));
+      OVFEM_HIP(hipMemsetAsync(g_mu, 0, s->n_elem * sizeof(double), s->stream));
+      OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 2 * vec * sizeof(double), s->stream));
+      double* w[2] = {wbuf.p, wbuf.p + vec};
+      int wc = 0, we = 0;  // w[wc] = w^{m+1}, w[wc ^ 1] = w^{m+2}
+      s->launch_exponents(w[0], wexp.p);
+
+      KArgs F = s->base_args();  // forward recompute: forward sources, no receivers
+      F.rec_nt = 0;
+      KArgs B = s->base_args();  // adjoint steps: residual injected at the receivers
+      B.src_ptr = d_aptr.p;
+      B.src_node = d_anode.p;
+      B.src_comp = d_acomp.p;
+      B.src_row = d_arow.p;
+      B.wavelet = residual;
+      B.src_nt = s->rec_nt;
+      B.rec_nt = 0;
+      const int gblocks = (int)((s->n_elem + NTHR - 1) / NTHR);
+
+      for (int64_t sg = (n - 1) / every; sg >= 0; --sg) {
+        const int64_t s0 = sg * every, e0 = std::min(s0 + every, n);
+        // state(k) = u^{s0+k}: slot 0 and u^{s0-1} from the checkpoint, the rest recomputed
+        auto state = [&](int64_t k) -> double* {
+          if (k < 0) return s->ckpt_u(sg, 1);
+          if (k == 0) return s->ckpt_u(sg, 0);
+          return seg.p + (size_t)k * vec;
+        };
+        int fe = 0;
+        s->launch_exponents(state(0), fexp.p);
+        for (int64_t t = s0; t < e0; ++t) {
+          F.u = state(t - s0);
+          F.uprev = state(t - s0 - 1);
+          F.unext = state(t - s0 + 1);
+          F.exp_in = fexp.p + fe * g.n_wg;
+          F.exp_out = fexp.p + (fe ^ 1) * g.n_wg;
+          F.step = t;
+          s->launch_layer(F, MODE_STEP);
+          fe ^= 1;
+        }
+        for (int64_t m = e0; m > s0; --m) {
+          B.u = w[wc];
+          B.uprev = w[wc ^ 1];
+          B.unext = w[wc ^ 1];
+          B.exp_in = wexp.p + we * g.n_wg;
+          B.exp_out = wexp.p + (we ^ 1) * g.n_wg;
+          B.step = m - 1;
+          s->launch_layer(B, MODE_STEP);
+          wc ^= 1;
+          we ^= 1;
+          ovfem_gradient_kernel<<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc], g_lam,
+                                                                 g_mu);
+          OVFEM_HIP(hipGetLastError());
+        }
+      }
+      OVFEM_HIP(hipStreamSynchronize(s->stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(s->stream);
+      free_all();
+      throw;
+    }
+    free_all();
   });
 }
 

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libovfem.so")
 
 OVFEM_FP64 = 0
 OVFEM_INT8 = 1
-PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8}
+OVFEM_INT8_I32 = 2
+PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8, "int8-i32": OVFEM_INT8_I32}
 
 # name -> (restype, argtypes); mirrors include/ovfem.h
 _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -38,6 +39,8 @@ SIGNATURES = {
     "ovfem_set_wavefield": (_i32, [_vp, _vp, _vp, _i64]),
     "ovfem_get_traces": (_i32, [_vp, _vp]),
     "ovfem_get_step": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "ovfem_set_checkpointing": (_i32, [_vp, _i64, _i64]),
+    "ovfem_adjoint": (_i32, [_vp, _vp, _vp, _vp]),
     "ovfem_synchronize": (_i32, [_vp]),
 }
 
@@ -101,6 +104,7 @@ class Solver:
                                  PRECISIONS[precision], ctypes.c_void_p(stream.cuda_stream)))
         self.n_rec = 0
         self.rec_nt = 0
+        self.dt = None
 
     def close(self):
         if self._h:
@@ -143,6 +147,7 @@ class Solver:
 
     def set_dt(self, dt):
         _check(_LIB.ovfem_set_dt(self._h, float(dt)))
+        self.dt = float(dt)
 
     def set_sources(self, node, comp, wavelet, shot=None):
         na, np_ = _host(node, np.int64)
@@ -209,6 +214,22 @@ class Solver:
             out = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")[:n]
         _check(_LIB.ovfem_get_traces(self._h, _dev_f64(out, n, "out") if n else None))
         return out.view(self.n_shots, self.n_rec, 3, self.rec_nt)
+
+    def set_checkpointing(self, every, max_steps):
+        _check(_LIB.ovfem_set_checkpointing(self._h, int(every), int(max_steps)))
+
+    def adjoint(self, residual):
+        """(g_lam, g_mu) as CUDA float64 tensors (nz, ny, nx) for dJ/d(traces) = residual."""
+        import torch
+        n = self.n_shots * self.n_rec * 3 * self.rec_nt
+        r = residual.reshape(-1)
+        ne = self.nx * self.ny * self.nz
+        g_lam = torch.empty(ne, dtype=torch.float64, device="cuda")
+        g_mu = torch.empty(ne, dtype=torch.float64, device="cuda")
+        _check(_LIB.ovfem_adjoint(self._h, _dev_f64(r, n, "residual"), _dev_f64(g_lam, ne, "g_lam"),
+                                  _dev_f64(g_mu, ne, "g_mu")))
+        shape = (self.nz, self.ny, self.nx)
+        return g_lam.view(shape), g_mu.view(shape)
 
     def get_step(self):
         v = ctypes.c_int64()

@@ -1,0 +1,134 @@
+"""GPU adjoint: against the oracle's discrete adjoint and against finite differences."""
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from paper_2404_13683_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "int8", "int8-i32"]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _case(nx=12, ny=10, nz=9, nt=60, seed=7):
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    h = 4.0
+    rho = rng.uniform(1900, 2400, shape)
+    vs = rng.uniform(500, 1100, shape)
+    lam, mu = wl.lame_from_velocities(2.0 * vs, vs, rho)
+    dt = wl.stable_dt(h, lam * 1.2, mu * 1.2, rho)
+    src = np.array([wl.node_id(nx // 2, ny // 2, nz, nx, ny)], np.int64)
+    rec = wl.surface_nodes(rng, 5, nx, ny, nz, exclude=src)
+    rec = np.concatenate([rec, [wl.node_id(3, 4, nz // 2, nx, ny)]])  # one buried receiver
+    w = wl.Workload("adjoint-case", nx, ny, nz, h, lam, mu, rho, wl.box_fixed(nx, ny, nz), dt, nt,
+                    src, np.array([2], np.int32), np.array([0], np.int32),
+                    wl.ricker(nt, dt, 1.0 / (18 * dt))[None, :], rec)
+    # observations from a perturbed "true" model (oracle forward)
+    lam_t = lam * (1 + 0.1 * rng.standard_normal(shape))
+    mu_t = mu * (1 + 0.1 * rng.standard_normal(shape))
+    mt = oasm.Model(lam_t, mu_t, rho, h, w.fixed, dt)
+    d_obs, *_ = oasm.simulate(mt, nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    return w, d_obs
+
+
+def _gpu_gradient(w, d_obs, prec, every):
+    import torch
+
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver.from_workload(w, precision=prec)
+    s.set_checkpointing(every, w.nt)
+    s.step(w.nt)
+    tr = s.get_traces()
+    res = (tr - torch.from_numpy(d_obs).cuda()[None]).contiguous()
+    g_lam, g_mu = s.adjoint(res)
+    out = (tr.cpu().numpy()[0], g_lam.cpu().numpy(), g_mu.cpu().numpy())
+    # the forward state is untouched by the adjoint
+    assert s.get_step() == w.nt
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gpu_adjoint_matches_oracle_adjoint(prec):
+    w, d_obs = _case()
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    J, gl_ref, gm_ref = oasm.adjoint_gradient(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node, d_obs)
+    tr, gl, gm = _gpu_gradient(w, d_obs, prec, every=7)
+    el, em = _rel(gl, gl_ref), _rel(gm, gm_ref)
+    print("adjoint %s: g_lam rel %.3e, g_mu rel %.3e" % (prec, el, em))
+    assert el <= 1e-9 and em <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8"])
+def test_gpu_adjoint_independent_of_checkpoint_interval(prec):
+    w, d_obs = _case(seed=8)
+    _, a_lam, a_mu = _gpu_gradient(w, d_obs, prec, every=5)
+    _, b_lam, b_mu = _gpu_gradient(w, d_obs, prec, every=w.nt)
+    assert np.array_equal(a_lam, b_lam) and np.array_equal(a_mu, b_mu)
+
+
+def test_gpu_adjoint_against_central_differences():
+    """Adjoint workload recipe at reduced size: FD on seeded voxels with |g| >= 1e-2 max |g|."""
+    import torch
+
+    from paper_2404_13683_amd.ovfem import Solver
+    true, start = wl.adjoint_c4(nx=24, ny=24, nz=20, nt=160, n_rec=12)
+    s = Solver.from_workload(true, precision="fp64")
+    s.step(true.nt)
+    d_obs = s.get_traces().clone()
+    s.close()
+    s = Solver.from_workload(start, precision="fp64")
+    s.set_checkpointing(40, start.nt)
+    s.step(start.nt)
+    res = (s.get_traces() - d_obs).contiguous()
+    g_lam, g_mu = (g.cpu().numpy() for g in s.adjoint(res))
+
+    def J(lam, mu):
+        s.set_model(lam, mu, start.rho)
+        s.set_dt(start.dt)
+        s.step(start.nt)
+        r = (s.get_traces() - d_obs).cpu().numpy()
+        return 0.5 * float(np.sum(r * r))
+
+    rng = np.random.default_rng(11)
+    checked = 0
+    for which, g in (("lam", g_lam), ("mu", g_mu)):
+        cand = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
+        for idx in cand[rng.choice(len(cand), size=5, replace=False)]:
+            k, j, i = map(int, idx)
+            lam, mu = start.lam.copy(), start.mu.copy()
+            arr = lam if which == "lam" else mu
+            base = arr[k, j, i]
+            eps = 1e-3 * base
+            arr[k, j, i] = base + eps
+            jp = J(lam, mu)
+            arr[k, j, i] = base - eps
+            jm = J(lam, mu)
+            fd = (jp - jm) / (2 * eps)
+            print("FD %s %s: adjoint %.6e fd %.6e" % (which, (k, j, i), g[k, j, i], fd))
+            assert abs(g[k, j, i] - fd) <= 1e-4 * abs(fd)
+            checked += 1
+    assert checked == 10
+
+
+def test_autograd_function_gives_the_adjoint_gradient():
+    import torch
+
+    from paper_2404_13683_amd import autograd
+    from paper_2404_13683_amd.ovfem import Solver
+    w, d_obs = _case(seed=9)
+    s = Solver.from_workload(w, precision="int8")
+    lam = torch.from_numpy(w.lam).cuda().requires_grad_(True)
+    mu = torch.from_numpy(w.mu).cuda().requires_grad_(True)
+    tr = autograd.traces(s, lam, mu, w.rho, nt=w.nt, ckpt_every=13)
+    J = 0.5 * ((tr[0] - torch.from_numpy(d_obs).cuda()) ** 2).sum()
+    J.backward()
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    _, gl_ref, gm_ref = oasm.adjoint_gradient(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node, d_obs)
+    assert _rel(lam.grad.cpu().numpy(), gl_ref) <= 1e-9
+    assert _rel(mu.grad.cpu().numpy(), gm_ref) <= 1e-9
