@@ -17,10 +17,10 @@
  *     per-tile power-of-two exponent, run the digit products on the matrix cores and
  *     recombine them into FP64 (Sec. 2, Eqs. (10)-(17), hierarchical FP64-INT64-INT8
  *     form); everything outside the digit products is FP64 (Sec. 3).  Two matrix-core
- *     forms give identical digit products: OVFEM_INT8 accumulates two digits per FP32
- *     accumulator on bf16 matrix cores (every operand and partial sum is an integer
- *     that bf16/FP32 represent exactly), OVFEM_INT8_I32 runs int8 matrix cores with
- *     INT32 accumulation.
+ *     forms give bitwise-identical results: OVFEM_INT8 runs int8 matrix cores with
+ *     INT32 accumulation; OVFEM_INT8_BF16 accumulates two digits per FP32 accumulator
+ *     on bf16 matrix cores (every operand and partial sum is an integer that bf16 and
+ *     FP32 represent exactly).
  *
  * Grid layout (shared by every array argument):
  *   elements e = i + nx (j + ny k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
@@ -57,10 +57,15 @@ typedef int32_t ovfem_status;
 
 /* precision of the element products */
 #define OVFEM_FP64 0
-#define OVFEM_INT8 1     /* INT8 digit slices, bf16 matrix cores, exact FP32 digit-pair sums */
-#define OVFEM_INT8_I32 2 /* INT8 digit slices, int8 matrix cores, INT32 accumulation */
+#define OVFEM_INT8 1      /* INT8 digit slices, int8 matrix cores, INT32 accumulation */
+#define OVFEM_INT8_BF16 2 /* INT8 digit slices, bf16 matrix cores, exact FP32 digit-pair sums */
+
+/* limits */
+#define OVFEM_MAX_SHOTS 4096 /* shots per solver */
+#define OVFEM_MAX_BATCH 4096 /* solvers per batch */
 
 typedef struct ovfem_solver ovfem_solver;
+typedef struct ovfem_batch ovfem_batch;
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int32_t ovfem_version(void);
@@ -70,18 +75,20 @@ int32_t ovfem_version(void);
 const char* ovfem_last_error(void);
 
 /* Create a solver for an nx x ny x nz voxel grid of edge h (> 0) on the current HIP
- * device.  n_shots must be 1.  stream is a
- * hipStream_t (NULL = the legacy default stream); all work is enqueued on it.
- * precision is OVFEM_FP64, OVFEM_INT8 or OVFEM_INT8_I32.
- * EINVAL for non-positive sizes, h <= 0, unknown precision; ENOMEM if the device
- * buffers do not fit. */
+ * device, stepping n_shots (1..OVFEM_MAX_SHOTS) independent wavefields of the same
+ * model at once (one per shot; every step of every shot runs in one kernel launch).
+ * stream is a hipStream_t (NULL = the legacy default stream); all work is enqueued on
+ * it.  precision is OVFEM_FP64, OVFEM_INT8 or OVFEM_INT8_BF16.
+ * Device memory: 2 n_shots nodal vectors + 16 bytes per element + 8 per node.
+ * EINVAL for non-positive sizes, h <= 0, unknown precision, n_shots out of range;
+ * ENOMEM if the device buffers do not fit. */
 ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz, double h,
                           int32_t n_shots, int32_t precision, void* stream);
 
 /* Free every device buffer of the solver (waits for its stream).  NULL is accepted. */
 ovfem_status ovfem_destroy(ovfem_solver* s);
 
-/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_I32). */
+/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_BF16). */
 ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision);
 
 /* Per-element material, HOST arrays of nx*ny*nz float64: Lame lam, shear modulus mu,
@@ -128,12 +135,13 @@ ovfem_status ovfem_step(ovfem_solver* s, int64_t n);
  * wavefield state of the solver is not touched.  Asynchronous on the stream. */
 ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku);
 
-/* Copy u^n (which = 0) or u^{n-1} (which = 1) into the DEVICE array out
- * ((nx+1)(ny+1)(nz+1)*3 float64).  Waits for the stream. */
+/* Copy u^n (which = 0) or u^{n-1} (which = 1) of every shot into the DEVICE array out
+ * (n_shots (nx+1)(ny+1)(nz+1)*3 float64, [shot][node][3]).  Waits for the stream. */
 ovfem_status ovfem_get_wavefield(ovfem_solver* s, int32_t which, double* out);
 
 /* Replace the state by (u^n = un, u^{n-1} = unm1) at step counter `step` (>= 0).
- * DEVICE arrays as in ovfem_get_wavefield.  Resumes a run from a saved state. */
+ * DEVICE arrays as in ovfem_get_wavefield (all shots).  Resumes a run from a saved
+ * state. */
 ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double* unm1, int64_t step);
 
 /* Recorded traces into the DEVICE array out, float64 laid out
@@ -148,7 +156,7 @@ ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step);
  * and, from now on, stores (u^s, u^{s-1}) on the device at every step s that is a
  * multiple of `every` (counted from reset).  every = 0 disables it.  Resets the
  * wavefield (as ovfem_reset).  Device memory: 2 (max_steps / every + 1) nodal vectors.
- * ENOMEM if it does not fit. */
+ * EINVAL with every > 0 on a solver of more than one shot; ENOMEM if it does not fit. */
 ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max_steps);
 
 /* Gradient of a receiver misfit with respect to the per-element lam and mu, by the
@@ -168,6 +176,52 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
  * precision for K.  The wavefield state and traces of the forward run are unchanged.
  * Synchronises the stream.  ESTATE if the preconditions do not hold. */
 ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_lam, double* g_mu);
+
+/* Launch configuration.  chunk_planes (1..4096): depth, in node planes, of the z-chunk a
+ * work-group marches through (the tiling is 15 x 15 node columns by about chunk_planes
+ * planes; default 16).  persistent_groups (>= 0): for n_shots > 1, cap on the launch
+ * grid, rounded down to a multiple of 8 (0 = one work-group per tile and shot).
+ * graph_steps (even, 0..4096; default 64): ovfem_step calls of at least that many steps
+ * replay a captured HIP graph of graph_steps steps instead of launching each step
+ * (0 = never; graphs are not used while checkpointing for the adjoint).  The FP64 path
+ * gives bitwise-identical results under every setting; the INT8 forms take their
+ * per-tile exponents over the tiling, so chunk_planes can change their last bits (their
+ * accuracy bound does not change).  Keeps the wavefield state; a changed tiling
+ * invalidates a checkpointed forward run.  EINVAL for out-of-range values. */
+ovfem_status ovfem_set_tuning(ovfem_solver* s, int32_t chunk_planes, int32_t persistent_groups,
+                              int32_t graph_steps);
+
+/* Current launch configuration (HOST out-pointers). */
+ovfem_status ovfem_get_tuning(ovfem_solver* s, int32_t* chunk_planes, int32_t* persistent_groups,
+                              int32_t* graph_steps);
+
+/* Autotuner: times `steps` (2..100000) plain-launch steps of the solver's own model,
+ * sources and precision for each candidate chunk depth (8, 12, 16, 24, 32 planes) and,
+ * for n_shots > 1, grid caps of 0, 2 and 4 work-groups per compute unit, and keeps the
+ * fastest (graph_steps unchanged).  The wavefield pair, traces and step counter are
+ * restored afterwards; a checkpointed forward run is invalidated.  best_ms_per_step
+ * (HOST, nullable) receives the best time per step in milliseconds.  Synchronises the
+ * stream.  ESTATE without model and dt. */
+ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_step);
+
+/* A batch of solvers of uneven grid sizes (and shot counts) stepped together: each
+ * ovfem_batch_step step is one kernel launch over the tiles of every shot of every
+ * member.  members: HOST array of n (1..OVFEM_MAX_BATCH) distinct solvers created on
+ * the same device with the same stream; they must outlive the batch.  The batch holds
+ * no wavefield state of its own: members keep theirs and may still be stepped alone. */
+ovfem_status ovfem_batch_create(ovfem_batch** out, ovfem_solver* const* members, int32_t n);
+
+/* Free the batch (waits for its stream; the members are untouched).  NULL is accepted. */
+ovfem_status ovfem_batch_destroy(ovfem_batch* b);
+
+/* Grid cap of the batched launch, as persistent_groups of ovfem_set_tuning (0 = none). */
+ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups);
+
+/* Enqueue n >= 0 steps of every member (asynchronous).  Each member advances exactly as
+ * ovfem_step(member, n) would (bitwise: the same kernels on the same tiles), from its
+ * own step counter.  Members must share one precision and have model and dt set
+ * (ESTATE otherwise).  Invalidates the members' checkpointed forward runs. */
+ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n);
 
 /* Wait for all work enqueued by the solver. */
 ovfem_status ovfem_synchronize(ovfem_solver* s);

@@ -17,21 +17,24 @@
 // matrices AL = 256 K_lam, AM = 128 K_mu (refmat.hpp):
 //   * FP64 path: one thread per element, dense 24 x 24 products in FP64 with the
 //     integer matrices as compile-time constants (the paper's "OVFEM FP64").
-//   * INT8 path (Sec. 2, Eqs. (10)-(17), reworked for CDNA4).  u is written as
+//   * INT8 paths (Sec. 2, Eqs. (10)-(17), reworked for CDNA4).  u is written as
 //     2^(E-62) q, q = floor(u 2^(62-E)) an integer with |q| <= 2^62, under one
 //     power-of-two exponent E per tile (the paper scales each element by s_e; a
 //     shared exponent lets a node's slices be computed once for its 8 elements, and
 //     the 62 bits keep every value within 2^9 of the tile maximum exact).  q is split
 //     into M = 8 balanced base-256 digits d_j in [-128, 127] (the paper: 8
-//     sign-magnitude base-128 digits of a 56-bit integer).  The digit products with
-//     the 48 x 24 integer matrix [AL; AM] run on the matrix cores, two digits per
-//     FP32 accumulator: A (256 d_{2p+1}) + A (d_{2p} + 128) is accumulated by two
-//     v_mfma_f32_16x16x32_bf16.  Every operand is an integer of at most 8
-//     significant bits (exact in bf16) and every partial sum an integer below
-//     384 * 128 * 256 + 384 * 255 < 2^24 (exact in FP32), so the pair sum is exact;
-//     the +128 bias on the low digit drops out because each row of K sums to zero
-//     (rigid translations).  The four pair sums are recombined in FP64 (Horner with
-//     factor 2^16) and scaled by h lam_e / 256 * 2^(E-62) and h mu_e / 128 * 2^(E-62).
+//     sign-magnitude base-128 digits of a 56-bit integer), and the digit products with
+//     the 48 x 24 integer matrix [AL; AM] run on the matrix cores, digits taken
+//     pairwise from the top.  PATH_INT8 uses v_mfma_i32_16x16x32_i8:
+//     C = A d_hi, C <<= 8, C += A d_lo, exact in INT32 since
+//     |C| <= 384 * 128 * 257 < 2^31 (the paper flushes INT32 every 3 stages).
+//     PATH_BF16 uses v_mfma_f32_16x16x32_bf16 with A (256 d_hi) + A (d_lo + 128) in
+//     one FP32 accumulator: every operand is an integer of at most 8 significant
+//     bits (exact in bf16) and every partial sum an integer below
+//     384 * 128 * 256 + 384 * 255 < 2^24 (exact in FP32); the +128 bias drops out
+//     because each row of K sums to zero (rigid translations).  Both give the same
+//     pair sums, which are recombined in FP64 (Horner with factor 2^16) and scaled by
+//     h lam_e / 256 * 2^(E-62) and h mu_e / 128 * 2^(E-62).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -65,9 +68,9 @@ static_assert(kMaxRowAbs * 128 * 256 + kMaxRowAbs * 255 < (1 << 24),
 static_assert((long long)kMaxRowAbs * 128 * 257 < 2147483647LL, "digit-pair sums must fit INT32");
 
 enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
-// PATH_INT8: digit pairs on bf16 matrix cores, exact FP32 accumulation;
-// PATH_I8: digits on i8 matrix cores, INT32 accumulation with a shift per pair.
-enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_I8 = 2 };
+// PATH_INT8: digits on i8 matrix cores, INT32 accumulation with a shift per pair;
+// PATH_BF16: digit pairs on bf16 matrix cores, exact FP32 accumulation.
+enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_BF16 = 2 };
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -104,7 +107,7 @@ struct KArgs {
   const int* rec_idx;     // receiver index
   double* traces;         // [rec][3][rec_nt]
   int src_nt, rec_nt;
-  long long step;         // index n of the step being taken
+  long long step;         // batch launches: the unit's step offset
 };
 
 // Logical tile of this work-group.  Work-groups are dealt to the 8 XCDs round-robin
@@ -285,10 +288,10 @@ __device__ inline void write_tile_exponent(double local_max, int* dst, double* r
   }
 }
 
+// One work-group tile (tile index wg of its unit) of one time step (or one matvec).
 template <int PATH, int MODE>
-__global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_kernel(KArgs A) {
+__device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const long long step) {
   const Geom g = A.g;
-  const int wg = logical_tile(blockIdx.x, g.n_wg);
   const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
   const int x0 = tx * TN, y0 = ty * TN, z0 = tzc * g.tz;
   const int z1 = min(z0 + g.tz, g.nz + 1);  // owned planes [z0, z1)
@@ -300,7 +303,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
   __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
   __shared__ double red[4];
   __shared__ __attribute__((aligned(16))) double matl[PATH == PATH_FP64 ? 2 : 2 * NTHR];  // slices: [b][a] material
-  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : (PATH == PATH_INT8 ? 2 * DPLANE * 4 : 2 * DPLANE8 * 4);
+  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * DPLANE8 * 4);
   __shared__ __attribute__((aligned(16))) unsigned char ring_raw[RING_BYTES];
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
@@ -320,11 +323,11 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
   }
   v8bf a_frag[3];
   long a_frag8[3];
-  if (PATH == PATH_INT8) {
+  if (PATH == PATH_BF16) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) a_frag[i] = __builtin_bit_cast(v8bf, A.alane[i * 64 + lane]);
   }
-  if (PATH == PATH_I8) {
+  if (PATH == PATH_INT8) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) a_frag8[i] = (long)A.alane8[i * 64 + lane];
   }
@@ -378,7 +381,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
       if (has_extra)
 #pragma unroll
         for (int c = 0; c < 3; ++c) P[(c * PN + xq) * PN + xp] = u_extra_next.v[c];
-    } else if (PATH == PATH_INT8) {
+    } else if (PATH == PATH_BF16) {
       uint32_t* P = ringd + slot * DPLANE;
       stage_digits(u_main_next, E, P + mq * DROW + 2 * mp);
       if (has_extra) stage_digits(u_extra_next, E, P + xq * DROW + 2 * xp);
@@ -453,7 +456,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
       for (int i = 0; i < 12; ++i) top_f[i] = y[12 + i];
     } else {
       const int ja = lane & 15, G = lane >> 4;  // element column; lane group
-      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_INT8 ? DPLANE : DPLANE8);
+      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_BF16 ? DPLANE : DPLANE8);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int b = 4 * wave + tt;
@@ -463,7 +466,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
           double R[12];
 #pragma unroll
           for (int p = NPAIR - 1; p >= 0; --p) {
-            if constexpr (PATH == PATH_INT8) {
+            if constexpr (PATH == PATH_BF16) {
               // the lane's eight K slots: (c0, c1, c2, 0) of node ja, then of node ja+1
               const uint32_t* P = Pin + (b + (G & 1)) * DROW + 2 * ja;
               const uint2* ph = reinterpret_cast<const uint2*>(P + (2 * p) * PN * 2);
@@ -568,8 +571,8 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
       } else {
         double F[3] = {0.0, 0.0, 0.0};
         for (int s = src_lo; s < src_hi; ++s)
-          if (A.src_node[s] == (int)nid && A.step < A.src_nt) {
-            const double w = A.wavelet[(long long)A.src_row[s] * A.src_nt + A.step];
+          if (A.src_node[s] == (int)nid && step < A.src_nt) {
+            const double w = A.wavelet[(long long)A.src_row[s] * A.src_nt + step];
             const int sc = A.src_comp[s];
             F[0] += sc == 0 ? w : 0.0;
             F[1] += sc == 1 ? w : 0.0;
@@ -585,8 +588,8 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
         o[2] = un[2];
         tile_max = fmax(tile_max, fmax(fabs(un[0]), fmax(fabs(un[1]), fabs(un[2]))));
         for (int r = rec_lo; r < rec_hi; ++r)
-          if (A.rec_node[r] == (int)nid && A.step < A.rec_nt) {
-            double* tr = A.traces + (long long)A.rec_idx[r] * 3 * A.rec_nt + A.step;
+          if (A.rec_node[r] == (int)nid && step < A.rec_nt) {
+            double* tr = A.traces + (long long)A.rec_idx[r] * 3 * A.rec_nt + step;
             tr[0] = un[0];
             tr[A.rec_nt] = un[1];
             tr[2 * A.rec_nt] = un[2];
@@ -595,6 +598,45 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2) ovfem_layer_k
     }
   }
   if (MODE == MODE_STEP) write_tile_exponent(tile_max, A.exp_out + wg, red);
+}
+
+// One unit (one shot of one grid): one work-group per tile.  The step index is
+// *step_base + step (step_base may be null), so a captured sequence of launches can
+// be replayed with a step base kept in device memory.
+template <int PATH, int MODE>
+__global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
+    ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
+  const long long s = (step_base ? *step_base : 0) + step;
+  layer_tile<PATH, MODE>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
+}
+
+// Many units in one launch (the shots of a grid, or grids of uneven size): unit u owns
+// work items [unit_begin[u], unit_begin[u+1]).  Work items are remapped so that each XCD
+// gets a contiguous run; a grid smaller than the work list strides over it (the grid
+// size is then a multiple of 8, so a work-group stays on one XCD's run).  The unit's
+// own step offset is units[u].step.
+template <int PATH, int MODE>
+__global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
+    ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
+                       const long long* step_base, long long step) {
+  const long long s = (step_base ? *step_base : 0) + step;
+  for (int b = blockIdx.x; b < total; b += gridDim.x) {
+    const int item = logical_tile(b, total);
+    int lo = 0, hi = n_units - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (unit_begin[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const KArgs A = units[lo];
+    layer_tile<PATH, MODE>(A, item - unit_begin[lo], s + A.step);
+    __syncthreads();  // LDS is reused by the next work item
+  }
+}
+
+// Adds n to the device step base (last node of a captured block of steps).
+__global__ void ovfem_advance_step_kernel(long long* step_base, long long n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
 }
 
 // Tile exponents of an arbitrary nodal vector (same tiling as the stepper).

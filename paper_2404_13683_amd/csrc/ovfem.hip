@@ -1,6 +1,7 @@
-// libovfem: C ABI of the OVFEM voxel stepper (see include/ovfem.h).
+// libovfem: C ABI of the OVFEM voxel stepper (declarations and contracts in ovfem.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -10,8 +11,8 @@
 #include <string>
 #include <vector>
 
-#include "ovfem.h"
 #include "kernels.hpp"
+#include "ovfem.h"
 
 using namespace ovfem;
 
@@ -55,6 +56,7 @@ ovfem_status guarded(F&& f) {
   }
 }
 
+// Device buffer; freed explicitly by its holder (swapped, never copied implicitly).
 template <class T>
 struct DevBuf {
   T* p = nullptr;
@@ -71,6 +73,13 @@ struct DevBuf {
     n = 0;
   }
 };
+
+template <class T>
+void upload(DevBuf<T>& dst, const std::vector<T>& src, hipStream_t stream) {
+  dst.alloc(src.size());
+  if (!src.empty())
+    OVFEM_HIP(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+}
 
 // Largest eigenvalue of a symmetric n x n matrix (cyclic Jacobi, host, small n).
 double max_eigenvalue(std::vector<double> a, int n) {
@@ -103,53 +112,106 @@ double max_eigenvalue(std::vector<double> a, int n) {
   return m;
 }
 
-// INT8 A fragments (bf16): lane l of row tile t holds A[i = l % 16][k = 8 (l / 16) .. + 7]
+// Matrix-core A operands: lane l of row tile t holds A[i = l % 16][k = 8 (l / 16) .. + 7]
 // of the 16 x 32 tile.  Row i of tile t is output s = 4 t + i % 4 for in-plane corner
 // G = i / 4: s < 6 are rows of AL, s >= 6 rows of AM, at corner G + 4 ((s % 6) / 3)
 // and component s % 3.  Column k is (node k / 4, component k % 4), component 3 padding.
-// Entries are integers of magnitude <= 98, exact in bf16.
-std::vector<uint32_t> make_alane() {
-  std::vector<uint32_t> out(3 * 64 * 4);
+int alane_entry(int t, int l, int q) {
+  const int i = l % 16, kg = l / 16;
+  const int G = i / 4, s = 4 * t + i % 4;
+  const int which = s / 6, dk = (s % 6) / 3, c = s % 3;
+  const int m = 3 * (G + 4 * dk) + c;
+  const int k = 8 * kg + q, node = k / 4, cp = k % 4;
+  if (cp == 3) return 0;
+  return which == 0 ? kRef.AL[m][3 * node + cp] : kRef.AM[m][3 * node + cp];
+}
+
+// bf16 form, two entries per 32-bit word: |entry| <= 127 has at most 7 significant
+// bits, so the upper half of its FP32 encoding is exact.
+std::vector<uint32_t> make_alane_bf16() {
+  std::vector<uint32_t> out(3 * 64 * 4, 0);
   for (int t = 0; t < 3; ++t)
-    for (int l = 0; l < 64; ++l) {
-      const int i = l % 16, kg = l / 16;
-      const int G = i / 4, s = 4 * t + i % 4;
-      const int which = s / 6, dk = (s % 6) / 3, c = s % 3;
-      const int m = 3 * (G + 4 * dk) + c;
+    for (int l = 0; l < 64; ++l)
       for (int q = 0; q < 8; ++q) {
-        const int k = 8 * kg + q, node = k / 4, cp = k % 4;
-        int v = 0;
-        if (cp < 3) v = which == 0 ? kRef.AL[m][3 * node + cp] : kRef.AM[m][3 * node + cp];
-        const float f = (float)v;
+        const float f = (float)alane_entry(t, l, q);
         uint32_t bits;
         std::memcpy(&bits, &f, 4);
-        const uint32_t bf = bits >> 16;  // exact: |v| <= 127 has <= 7 significant bits
-        out[(t * 64 + l) * 4 + q / 2] |= bf << (16 * (q % 2));
+        out[(t * 64 + l) * 4 + q / 2] |= (bits >> 16) << (16 * (q % 2));
       }
-    }
   return out;
 }
 
-// I8 A fragments: the same matrix entries as make_alane(), as int8 bytes.
-std::vector<uint64_t> make_alane8() {
+// int8 form, eight entries per 64-bit word.
+std::vector<uint64_t> make_alane_i8() {
   std::vector<uint64_t> out(3 * 64, 0);
   for (int t = 0; t < 3; ++t)
-    for (int l = 0; l < 64; ++l) {
-      const int i = l % 16, kg = l / 16;
-      const int G = i / 4, s = 4 * t + i % 4;
-      const int which = s / 6, dk = (s % 6) / 3, c = s % 3;
-      const int m = 3 * (G + 4 * dk) + c;
-      for (int q = 0; q < 8; ++q) {
-        const int k = 8 * kg + q, node = k / 4, cp = k % 4;
-        int v = 0;
-        if (cp < 3) v = which == 0 ? kRef.AL[m][3 * node + cp] : kRef.AM[m][3 * node + cp];
-        out[t * 64 + l] |= (uint64_t)(uint8_t)(int8_t)v << (8 * q);
-      }
-    }
+    for (int l = 0; l < 64; ++l)
+      for (int q = 0; q < 8; ++q)
+        out[t * 64 + l] |= (uint64_t)(uint8_t)(int8_t)alane_entry(t, l, q) << (8 * q);
   return out;
 }
 
-bool valid_precision(int p) { return p == OVFEM_FP64 || p == OVFEM_INT8 || p == OVFEM_INT8_I32; }
+bool valid_precision(int p) { return p == OVFEM_FP64 || p == OVFEM_INT8 || p == OVFEM_INT8_BF16; }
+
+// One unit, one work-group per tile.
+template <int MODE>
+void launch_unit(int precision, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
+  const dim3 grid(A.g.n_wg), block(NTHR);
+  if (precision == OVFEM_FP64)
+    ovfem_layer_kernel<PATH_FP64, MODE><<<grid, block, 0, stream>>>(A, base, step);
+  else if (precision == OVFEM_INT8)
+    ovfem_layer_kernel<PATH_INT8, MODE><<<grid, block, 0, stream>>>(A, base, step);
+  else
+    ovfem_layer_kernel<PATH_BF16, MODE><<<grid, block, 0, stream>>>(A, base, step);
+  OVFEM_HIP(hipGetLastError());
+}
+
+// Many units in one launch; grid_cap > 0 caps the grid (rounded down to a multiple of
+// 8, at least 8) so that the work-groups stride over the work list.
+void launch_units(int precision, const KArgs* units, const int* begin, int n_units, int total, int grid_cap,
+                  const long long* base, long long step, hipStream_t stream) {
+  int grid = total;
+  if (grid_cap > 0 && grid_cap < total) grid = std::max(8, (grid_cap / 8) * 8);
+  const dim3 g(grid), block(NTHR);
+  if (precision == OVFEM_FP64)
+    ovfem_batch_kernel<PATH_FP64, MODE_STEP><<<g, block, 0, stream>>>(units, begin, n_units, total, base, step);
+  else if (precision == OVFEM_INT8)
+    ovfem_batch_kernel<PATH_INT8, MODE_STEP><<<g, block, 0, stream>>>(units, begin, n_units, total, base, step);
+  else
+    ovfem_batch_kernel<PATH_BF16, MODE_STEP><<<g, block, 0, stream>>>(units, begin, n_units, total, base, step);
+  OVFEM_HIP(hipGetLastError());
+}
+
+// Tiling: 15 x 15 owned node columns per work-group, node planes split into chunks of
+// equal depth close to chunk_planes.
+Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int chunk_planes) {
+  Geom g{};
+  g.nx = (int)nx;
+  g.ny = (int)ny;
+  g.nz = (int)nz;
+  g.tiles_x = (int)((nx + 1 + TN - 1) / TN);
+  g.tiles_y = (int)((ny + 1 + TN - 1) / TN);
+  const int64_t target = std::max(1, chunk_planes);
+  g.chunks = (int)((nz + 1 + target - 1) / target);
+  g.tz = (int)((nz + 1 + g.chunks - 1) / g.chunks);
+  g.chunks = (int)((nz + 1 + g.tz - 1) / g.tz);
+  g.n_wg = g.tiles_x * g.tiles_y * g.chunks;
+  return g;
+}
+
+// Per-tile CSR tables of sources (per shot) and receivers (shared by the shots).
+struct SourceTables {
+  DevBuf<int> ptr, node, comp, row;
+  void free() {
+    for (auto* b : {&ptr, &node, &comp, &row}) b->free();
+  }
+};
+struct ReceiverTables {
+  DevBuf<int> ptr, node, idx;
+  void free() {
+    for (auto* b : {&ptr, &node, &idx}) b->free();
+  }
+};
 
 }  // namespace
 
@@ -163,27 +225,26 @@ struct ovfem_solver {
   Geom geom{};
   size_t n_nodes = 0, n_elem = 0;
 
+  // state: u[cur] = u^n and u[cur ^ 1] = u^{n-1}, [shot][node][3]; expo[cur] holds the
+  // tile exponents of u^n, [shot][tile]
   DevBuf<double> u[2];
-  int cur = 0;  // u[cur] = u^n, u[cur ^ 1] = u^{n-1}
-  DevBuf<double> mat, acoef;  // mat: [element][2] = (h lam / 256, h mu / 128)
-  DevBuf<int> expo[2], expo_tmp;
-  int exp_cur = 0;
+  DevBuf<int> expo[2];
+  int cur = 0;
   bool exp_valid = false;
-  DevBuf<uint32_t> alane;
-  DevBuf<uint64_t> alane8;
+  DevBuf<int> expo_tmp;          // exponents of a matvec operand
+  DevBuf<double> mat, acoef;     // mat: [element][2] = (h lam / 256, h mu / 128)
+  DevBuf<uint32_t> alane_bf16;
+  DevBuf<uint64_t> alane_i8;
 
-  DevBuf<int> src_ptr, src_node, src_comp, src_row;
-  DevBuf<double> wavelet;
+  SourceTables src;              // ptr: [shot][n_wg + 1]
+  DevBuf<double> wavelet;        // [n_src][src_nt]
   int src_nt = 0, n_src = 0;
-  DevBuf<int> rec_ptr, rec_node, rec_idx;
-  DevBuf<double> traces;
+  std::vector<int64_t> src_node_h;
+  std::vector<int32_t> src_comp_h, src_shot_h;
+  ReceiverTables rec;
+  DevBuf<double> traces;         // [shot][rec][3][rec_nt]
   int rec_nt = 0, n_rec = 0;
-
-  // adjoint: forward checkpoints (u^s, u^{s-1}) at s = 0, every, 2 every, ... since reset
-  int64_t ckpt_every = 0, ckpt_slots = 0;
-  DevBuf<double> ckpt;           // [slot][2][3 n_nodes]
-  bool ckpt_valid = false;       // the run since reset was checkpointed with this precision
-  int ckpt_precision = OVFEM_FP64;
+  std::vector<int64_t> rec_node_h;
 
   std::vector<double> mass;      // nodal mass (host)
   std::vector<uint8_t> fixed;    // nodal fixed flags (host)
@@ -191,39 +252,60 @@ struct ovfem_solver {
   double dt = 0, dt_bound = 0;
   int64_t step = 0;
 
+  // adjoint: forward checkpoints (u^s, u^{s-1}) at s = 0, every, 2 every, ... since reset
+  int64_t ckpt_every = 0, ckpt_slots = 0;
+  DevBuf<double> ckpt;           // [slot][2][3 n_nodes]
+  bool ckpt_valid = false;       // the run since reset was checkpointed with this precision
+  int ckpt_precision = OVFEM_FP64;
+
+  // launch configuration
+  int chunk_planes = 16, persist_groups = 0, graph_steps = 64;
+  DevBuf<KArgs> units;           // [parity][shot]: arguments of each shot, u^n in buffer parity
+  DevBuf<int> unit_begin;        // [shot + 1]: first work item of each shot
+  DevBuf<long long> step_base;   // step index of the next replay of a captured block
+  bool tables_dirty = true;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // captured block starting from u[parity]
+  int graph_precision[2] = {-1, -1};
+
   ~ovfem_solver() {
     (void)hipStreamSynchronize(stream);
-    u[0].free();
-    u[1].free();
-    mat.free();
-    acoef.free();
-    expo[0].free();
-    expo[1].free();
-    expo_tmp.free();
-    alane.free();
-    alane8.free();
-    src_ptr.free();
-    src_node.free();
-    src_comp.free();
-    src_row.free();
-    wavelet.free();
-    rec_ptr.free();
-    rec_node.free();
-    rec_idx.free();
-    traces.free();
-    ckpt.free();
+    drop_graphs();
+    for (auto* b : {&u[0], &u[1], &mat, &acoef, &wavelet, &traces, &ckpt}) b->free();
+    for (auto* b : {&expo[0], &expo[1], &expo_tmp, &unit_begin}) b->free();
+    src.free();
+    rec.free();
+    alane_bf16.free();
+    alane_i8.free();
+    units.free();
+    step_base.free();
   }
 
-  double* ckpt_u(int64_t slot, int which) { return ckpt.p + (size_t)(2 * slot + which) * 3 * n_nodes; }
-
-  int tile_of(int64_t X, int64_t Y, int64_t Z) const {
-    return (int)(X / TN + geom.tiles_x * (Y / TN + geom.tiles_y * (Z / geom.tz)));
-  }
+  size_t vec() const { return 3 * n_nodes; }
+  double* ckpt_u(int64_t slot, int which) { return ckpt.p + (size_t)(2 * slot + which) * vec(); }
 
   void check_device() {
     int d = -1;
     OVFEM_HIP(hipGetDevice(&d));
     require(d == device, "solver used on a different current device than it was created on", OVFEM_ESTATE);
+  }
+
+  void drop_graphs() {
+    for (int p = 0; p < 2; ++p) {
+      if (graph[p]) (void)hipGraphExecDestroy(graph[p]);
+      graph[p] = nullptr;
+      graph_precision[p] = -1;
+    }
+  }
+  // launch arguments changed (pointers, tiling, sources, receivers)
+  void invalidate_launches() {
+    tables_dirty = true;
+    drop_graphs();
+  }
+
+  static int tile_of(const Geom& g, int64_t node) {
+    const int64_t X = node % (g.nx + 1), Y = (node / (g.nx + 1)) % (g.ny + 1),
+                  Z = node / ((int64_t)(g.nx + 1) * (g.ny + 1));
+    return (int)(X / TN + g.tiles_x * (Y / TN + (int64_t)g.tiles_y * (Z / g.tz)));
   }
 
   void refresh_acoef() {
@@ -236,103 +318,260 @@ struct ovfem_solver {
     acoef_dirty = false;
   }
 
-  void launch_exponents(const double* v, int* dst) {
-    ovfem_exponent_kernel<<<geom.n_wg, NTHR, 0, stream>>>(geom, v, dst);
-    OVFEM_HIP(hipGetLastError());
+  void launch_exponents(const Geom& g, const double* v, int* dst, int shots) {
+    for (int s = 0; s < shots; ++s) {
+      ovfem_exponent_kernel<<<g.n_wg, NTHR, 0, stream>>>(g, v + (size_t)s * vec(), dst + (size_t)s * g.n_wg);
+      OVFEM_HIP(hipGetLastError());
+    }
   }
 
-  KArgs base_args() const {
+  // source lists of every (shot, tile) for tiling g; rows index the wavelet table
+  SourceTables build_sources(const Geom& g, const std::vector<int64_t>& node, const std::vector<int32_t>& comp,
+                             const std::vector<int32_t>& shot) const {
+    const int nwg = g.n_wg, S = n_shots;
+    std::vector<std::vector<int>> per((size_t)S * nwg);
+    for (size_t i = 0; i < node.size(); ++i) per[(size_t)shot[i] * nwg + tile_of(g, node[i])].push_back((int)i);
+    std::vector<int> ptr((size_t)S * (nwg + 1), 0), nd, cp, row;
+    for (int s = 0; s < S; ++s) {
+      int* p = ptr.data() + (size_t)s * (nwg + 1);
+      p[0] = (int)nd.size();
+      for (int w = 0; w < nwg; ++w) {
+        for (int i : per[(size_t)s * nwg + w]) {
+          nd.push_back((int)node[i]);
+          cp.push_back(comp[i]);
+          row.push_back(i);
+        }
+        p[w + 1] = (int)nd.size();
+      }
+    }
+    SourceTables t;
+    try {
+      upload(t.ptr, ptr, stream);
+      upload(t.node, nd, stream);
+      upload(t.comp, cp, stream);
+      upload(t.row, row, stream);
+      OVFEM_HIP(hipStreamSynchronize(stream));
+    } catch (...) {
+      t.free();
+      throw;
+    }
+    return t;
+  }
+
+  ReceiverTables build_receivers(const Geom& g, const std::vector<int64_t>& node) const {
+    const int nwg = g.n_wg;
+    std::vector<std::vector<int>> per(nwg);
+    for (size_t i = 0; i < node.size(); ++i) per[tile_of(g, node[i])].push_back((int)i);
+    std::vector<int> ptr(nwg + 1, 0), nd, idx;
+    for (int w = 0; w < nwg; ++w) {
+      for (int i : per[w]) {
+        nd.push_back((int)node[i]);
+        idx.push_back(i);
+      }
+      ptr[w + 1] = (int)nd.size();
+    }
+    ReceiverTables t;
+    try {
+      upload(t.ptr, ptr, stream);
+      upload(t.node, nd, stream);
+      upload(t.idx, idx, stream);
+      OVFEM_HIP(hipStreamSynchronize(stream));
+    } catch (...) {
+      t.free();
+      throw;
+    }
+    return t;
+  }
+
+  // the arguments of one shot with u^n in buffer `parity`
+  KArgs shot_args(int shot, int parity) const {
     KArgs A{};
     A.g = geom;
+    A.u = u[parity].p + (size_t)shot * vec();
+    A.uprev = u[parity ^ 1].p + (size_t)shot * vec();
+    A.unext = u[parity ^ 1].p + (size_t)shot * vec();
     A.mat = mat.p;
     A.acoef = acoef.p;
-    A.alane = reinterpret_cast<const v4u*>(alane.p);
-    A.alane8 = alane8.p;
-    A.src_ptr = src_ptr.p;
-    A.src_node = src_node.p;
-    A.src_comp = src_comp.p;
-    A.src_row = src_row.p;
+    A.exp_in = expo[parity].p + (size_t)shot * geom.n_wg;
+    A.exp_out = expo[parity ^ 1].p + (size_t)shot * geom.n_wg;
+    A.alane = reinterpret_cast<const v4u*>(alane_bf16.p);
+    A.alane8 = alane_i8.p;
+    A.src_ptr = src.ptr.p + (size_t)shot * (geom.n_wg + 1);
+    A.src_node = src.node.p;
+    A.src_comp = src.comp.p;
+    A.src_row = src.row.p;
     A.wavelet = wavelet.p;
     A.src_nt = src_nt;
-    A.rec_ptr = rec_ptr.p;
-    A.rec_node = rec_node.p;
-    A.rec_idx = rec_idx.p;
-    A.traces = traces.p;
+    A.rec_ptr = rec.ptr.p;
+    A.rec_node = rec.node.p;
+    A.rec_idx = rec.idx.p;
+    A.traces = traces.p + (size_t)shot * n_rec * 3 * rec_nt;
     A.rec_nt = rec_nt;
+    A.step = 0;
     return A;
   }
 
-  void launch_layer(const KArgs& A, int mode) {
-    const dim3 grid(geom.n_wg), block(NTHR);
-    if (precision == OVFEM_FP64) {
-      if (mode == MODE_STEP)
-        ovfem_layer_kernel<PATH_FP64, MODE_STEP><<<grid, block, 0, stream>>>(A);
-      else
-        ovfem_layer_kernel<PATH_FP64, MODE_MATVEC><<<grid, block, 0, stream>>>(A);
-    } else if (precision == OVFEM_INT8) {
-      if (mode == MODE_STEP)
-        ovfem_layer_kernel<PATH_INT8, MODE_STEP><<<grid, block, 0, stream>>>(A);
-      else
-        ovfem_layer_kernel<PATH_INT8, MODE_MATVEC><<<grid, block, 0, stream>>>(A);
-    } else {
-      if (mode == MODE_STEP)
-        ovfem_layer_kernel<PATH_I8, MODE_STEP><<<grid, block, 0, stream>>>(A);
-      else
-        ovfem_layer_kernel<PATH_I8, MODE_MATVEC><<<grid, block, 0, stream>>>(A);
+  void refresh_tables() {
+    if (!tables_dirty) return;
+    std::vector<KArgs> t((size_t)2 * n_shots);
+    for (int p = 0; p < 2; ++p)
+      for (int s = 0; s < n_shots; ++s) t[(size_t)p * n_shots + s] = shot_args(s, p);
+    std::vector<int> begin(n_shots + 1);
+    for (int s = 0; s <= n_shots; ++s) begin[s] = s * geom.n_wg;
+    OVFEM_HIP(hipStreamSynchronize(stream));  // earlier launches may still read the old tables
+    upload(units, t, stream);
+    upload(unit_begin, begin, stream);
+    OVFEM_HIP(hipStreamSynchronize(stream));
+    tables_dirty = false;
+  }
+
+  // one step of every shot with u^n in buffer `parity`; step index *base + step_arg
+  void launch_step(hipStream_t st, int parity, const long long* base, long long step_arg) {
+    if (n_shots == 1)
+      launch_unit<MODE_STEP>(precision, shot_args(0, parity), base, step_arg, st);
+    else
+      launch_units(precision, units.p + (size_t)parity * n_shots, unit_begin.p, n_shots, n_shots * geom.n_wg,
+                   persist_groups, base, step_arg, st);
+  }
+
+  // capture graph_steps (even) steps starting from buffer parity p, followed by the
+  // advance of the device step base; the parity is p again after the block
+  void capture_graph(int p) {
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    OVFEM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    try {
+      OVFEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int i = 0; i < graph_steps; ++i) launch_step(cs, p ^ (i & 1), step_base.p, i);
+        ovfem_advance_step_kernel<<<1, 64, 0, cs>>>(step_base.p, graph_steps);
+        OVFEM_HIP(hipGetLastError());
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &g);
+        throw;
+      }
+      OVFEM_HIP(hipStreamEndCapture(cs, &g));
+      OVFEM_HIP(hipGraphInstantiate(&graph[p], g, nullptr, nullptr, 0));
+      graph_precision[p] = precision;
+    } catch (...) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      throw;
     }
-    OVFEM_HIP(hipGetLastError());
+    (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
   }
 
   void zero_state() {
-    OVFEM_HIP(hipMemsetAsync(u[0].p, 0, 3 * n_nodes * sizeof(double), stream));
-    OVFEM_HIP(hipMemsetAsync(u[1].p, 0, 3 * n_nodes * sizeof(double), stream));
+    const size_t bytes = (size_t)n_shots * vec() * sizeof(double);
+    OVFEM_HIP(hipMemsetAsync(u[0].p, 0, bytes, stream));
+    OVFEM_HIP(hipMemsetAsync(u[1].p, 0, bytes, stream));
     if (traces.p) OVFEM_HIP(hipMemsetAsync(traces.p, 0, traces.n * sizeof(double), stream));
     cur = 0;
     step = 0;
-    launch_exponents(u[cur].p, expo[exp_cur].p);
+    launch_exponents(geom, u[cur].p, expo[cur].p, n_shots);
     exp_valid = true;
     ckpt_valid = ckpt_every > 0;
     ckpt_precision = precision;
   }
 
-  void do_steps(int64_t n) {
+  void prepare_steps() {
     require(model_set, "ovfem_step: model not set", OVFEM_ESTATE);
     require(dt_set, "ovfem_step: dt not set", OVFEM_ESTATE);
     refresh_acoef();
     if (!exp_valid) {
-      launch_exponents(u[cur].p, expo[exp_cur].p);
+      launch_exponents(geom, u[cur].p, expo[cur].p, n_shots);
       exp_valid = true;
     }
-    KArgs A = base_args();
+    refresh_tables();
+  }
+
+  void do_steps(int64_t n) {
+    prepare_steps();
     if (ckpt_valid && precision != ckpt_precision) ckpt_valid = false;
-    for (int64_t i = 0; i < n; ++i) {
+    int64_t done = 0;
+    if (graph_steps > 0 && !ckpt_valid && n >= graph_steps) {
+      if (!graph[cur] || graph_precision[cur] != precision) {
+        if (graph[cur]) (void)hipGraphExecDestroy(graph[cur]);
+        graph[cur] = nullptr;
+        capture_graph(cur);
+      }
+      const long long s0 = step;
+      OVFEM_HIP(hipMemcpyAsync(step_base.p, &s0, sizeof(long long), hipMemcpyHostToDevice, stream));
+      OVFEM_HIP(hipStreamSynchronize(stream));  // s0 is a host stack value
+      for (; done + graph_steps <= n; done += graph_steps) OVFEM_HIP(hipGraphLaunch(graph[cur], stream));
+      step += done;  // an even count: cur is unchanged
+    }
+    for (; done < n; ++done) {
       if (ckpt_valid && step % ckpt_every == 0) {
         const int64_t slot = step / ckpt_every;
         if (slot < ckpt_slots) {
-          const size_t bytes = 3 * n_nodes * sizeof(double);
+          const size_t bytes = vec() * sizeof(double);
           OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 0), u[cur].p, bytes, hipMemcpyDeviceToDevice, stream));
           OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 1), u[cur ^ 1].p, bytes, hipMemcpyDeviceToDevice, stream));
         } else {
           ckpt_valid = false;  // ran past the checkpoint capacity
         }
       }
-      A.u = u[cur].p;
-      A.uprev = u[cur ^ 1].p;
-      A.unext = u[cur ^ 1].p;
-      A.exp_in = expo[exp_cur].p;
-      A.exp_out = expo[exp_cur ^ 1].p;
-      A.step = step;
-      launch_layer(A, MODE_STEP);
+      launch_step(stream, cur, nullptr, step);
       cur ^= 1;
-      exp_cur ^= 1;
       ++step;
     }
+  }
+
+  // change the z-chunk depth: new tiling, tile lists and exponents; the state is kept
+  void retile(int planes) {
+    const Geom g = make_geom(nx, ny, nz, planes);
+    DevBuf<int> e0, e1, et;
+    SourceTables st;
+    ReceiverTables rt;
+    try {
+      e0.alloc((size_t)n_shots * g.n_wg);
+      e1.alloc((size_t)n_shots * g.n_wg);
+      et.alloc(g.n_wg);
+      st = build_sources(g, src_node_h, src_comp_h, src_shot_h);
+      rt = build_receivers(g, rec_node_h);
+    } catch (...) {
+      for (auto* b : {&e0, &e1, &et}) b->free();
+      st.free();
+      rt.free();
+      throw;
+    }
+    OVFEM_HIP(hipStreamSynchronize(stream));
+    std::swap(expo[0], e0);
+    std::swap(expo[1], e1);
+    std::swap(expo_tmp, et);
+    std::swap(src, st);
+    std::swap(rec, rt);
+    for (auto* b : {&e0, &e1, &et}) b->free();
+    st.free();
+    rt.free();
+    geom = g;
+    chunk_planes = planes;
+    launch_exponents(geom, u[cur].p, expo[cur].p, n_shots);
+    exp_valid = true;
+    ckpt_valid = false;  // the INT8 exponent granularity follows the tiling
+    invalidate_launches();
+    OVFEM_HIP(hipStreamSynchronize(stream));
+  }
+};
+
+struct ovfem_batch {
+  std::vector<ovfem_solver*> members;
+  hipStream_t stream = nullptr;
+  int persist_groups = 0;
+  DevBuf<KArgs> units;  // [relative parity][unit]
+  DevBuf<int> begin;    // [unit + 1]
+  ~ovfem_batch() {
+    (void)hipStreamSynchronize(stream);
+    units.free();
+    begin.free();
   }
 };
 
 extern "C" {
 
-int32_t ovfem_version(void) { return 100; }
+int32_t ovfem_version(void) { return 200; }
 
 const char* ovfem_last_error(void) { return g_last_error.c_str(); }
 
@@ -343,7 +582,7 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
     *out = nullptr;
     require(nx > 0 && ny > 0 && nz > 0, "ovfem_create: grid sizes must be positive");
     require(std::isfinite(h) && h > 0, "ovfem_create: h must be positive");
-    require(n_shots == 1, "ovfem_create: n_shots must be 1");
+    require(n_shots >= 1 && n_shots <= OVFEM_MAX_SHOTS, "ovfem_create: n_shots out of range");
     require(valid_precision(precision), "ovfem_create: unknown precision");
     const double nn = double(nx + 1) * double(ny + 1) * double(nz + 1);
     require(nn < 2147483647.0, "ovfem_create: more than 2^31 - 1 nodes");
@@ -355,44 +594,26 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
       s->ny = ny;
       s->nz = nz;
       s->h = h;
+      s->n_shots = n_shots;
       s->precision = precision;
       s->n_nodes = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
       s->n_elem = (size_t)nx * ny * nz;
-      Geom& g = s->geom;
-      g.nx = (int)nx;
-      g.ny = (int)ny;
-      g.nz = (int)nz;
-      g.tiles_x = (int)((nx + 1 + TN - 1) / TN);
-      g.tiles_y = (int)((ny + 1 + TN - 1) / TN);
-      g.chunks = (int)((nz + 1 + 15) / 16);
-      g.tz = (int)((nz + 1 + g.chunks - 1) / g.chunks);
-      g.chunks = (int)((nz + 1 + g.tz - 1) / g.tz);
-      g.n_wg = g.tiles_x * g.tiles_y * g.chunks;
-      s->u[0].alloc(3 * s->n_nodes);
-      s->u[1].alloc(3 * s->n_nodes);
+      s->geom = make_geom(nx, ny, nz, s->chunk_planes);
+      const Geom& g = s->geom;
+      s->u[0].alloc((size_t)n_shots * s->vec());
+      s->u[1].alloc((size_t)n_shots * s->vec());
       s->mat.alloc(2 * s->n_elem);
       s->acoef.alloc(s->n_nodes);
-      s->expo[0].alloc(g.n_wg);
-      s->expo[1].alloc(g.n_wg);
+      s->expo[0].alloc((size_t)n_shots * g.n_wg);
+      s->expo[1].alloc((size_t)n_shots * g.n_wg);
       s->expo_tmp.alloc(g.n_wg);
-      auto al = make_alane();
-      s->alane.alloc(al.size());
-      OVFEM_HIP(hipMemcpyAsync(s->alane.p, al.data(), al.size() * 4, hipMemcpyHostToDevice, s->stream));
-      auto al8 = make_alane8();
-      s->alane8.alloc(al8.size());
-      OVFEM_HIP(hipMemcpyAsync(s->alane8.p, al8.data(), al8.size() * 8, hipMemcpyHostToDevice, s->stream));
-      std::vector<int> zeros(g.n_wg + 1, 0);
-      s->src_ptr.alloc(g.n_wg + 1);
-      s->rec_ptr.alloc(g.n_wg + 1);
-      OVFEM_HIP(hipMemcpyAsync(s->src_ptr.p, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(s->rec_ptr.p, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, s->stream));
-      s->src_node.alloc(1);
-      s->src_comp.alloc(1);
-      s->src_row.alloc(1);
+      s->step_base.alloc(1);
+      upload(s->alane_bf16, make_alane_bf16(), s->stream);
+      upload(s->alane_i8, make_alane_i8(), s->stream);
       s->wavelet.alloc(1);
-      s->rec_node.alloc(1);
-      s->rec_idx.alloc(1);
       s->traces.alloc(1);
+      s->src = s->build_sources(g, {}, {}, {});
+      s->rec = s->build_receivers(g, {});
       s->mass.assign(s->n_nodes, 0.0);
       s->fixed.assign(s->n_nodes, 0);
       s->zero_state();
@@ -461,6 +682,7 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
                 mass[(size_t)((i + di) + (nx + 1) * ((j + dj) + (ny + 1) * (k + dk)))] += me;
         }
     s->dt_bound = wmax2 > 0 ? 2.0 / std::sqrt(wmax2) : std::numeric_limits<double>::infinity();
+    OVFEM_HIP(hipStreamSynchronize(s->stream));  // earlier steps may still read mat
     OVFEM_HIP(hipMemcpyAsync(s->mat.p, mt.data(), 2 * ne * sizeof(double), hipMemcpyHostToDevice, s->stream));
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     s->mass.swap(mass);
@@ -502,52 +724,39 @@ ovfem_status ovfem_set_sources(ovfem_solver* s, int32_t n, const int64_t* node, 
     require(n >= 0, "ovfem_set_sources: n < 0");
     require(n == 0 || (node && comp && wavelet && nt > 0), "ovfem_set_sources: missing arrays or nt <= 0");
     require((double)n * (double)std::max<int64_t>(nt, 1) < 2147483647.0, "ovfem_set_sources: table too large");
-    const int nwg = s->geom.n_wg;
-    std::vector<std::vector<int>> per(nwg);
+    std::vector<int64_t> nd(n);
+    std::vector<int32_t> cp(n), sh(n);
     for (int i = 0; i < n; ++i) {
       require(node[i] >= 0 && (size_t)node[i] < s->n_nodes, "ovfem_set_sources: node out of range");
       require(comp[i] >= 0 && comp[i] < 3, "ovfem_set_sources: comp out of range");
       require(shot == nullptr || (shot[i] >= 0 && shot[i] < s->n_shots), "ovfem_set_sources: shot out of range");
-      const int64_t X = node[i] % (s->nx + 1), Y = (node[i] / (s->nx + 1)) % (s->ny + 1),
-                    Z = node[i] / ((s->nx + 1) * (s->ny + 1));
-      per[s->tile_of(X, Y, Z)].push_back(i);
+      nd[i] = node[i];
+      cp[i] = comp[i];
+      sh[i] = shot ? shot[i] : 0;
     }
-    std::vector<int> ptr(nwg + 1, 0), nd, cp, row;
-    for (int w = 0; w < nwg; ++w) {
-      ptr[w + 1] = ptr[w] + (int)per[w].size();
-      for (int i : per[w]) {
-        nd.push_back((int)node[i]);
-        cp.push_back(comp[i]);
-        row.push_back(i);
-      }
-    }
-    DevBuf<int> dptr, dnd, dcp, drow;
+    SourceTables st;
     DevBuf<double> dw;
-    dptr.alloc(nwg + 1);
-    dnd.alloc(nd.size());
-    dcp.alloc(cp.size());
-    drow.alloc(row.size());
-    dw.alloc((size_t)n * (size_t)std::max<int64_t>(nt, 1));
-    OVFEM_HIP(hipMemcpyAsync(dptr.p, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s->stream));
-    if (n > 0) {
-      OVFEM_HIP(hipMemcpyAsync(dnd.p, nd.data(), nd.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(dcp.p, cp.data(), cp.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(drow.p, row.data(), row.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(dw.p, wavelet, (size_t)n * nt * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    try {
+      st = s->build_sources(s->geom, nd, cp, sh);
+      dw.alloc((size_t)n * (size_t)std::max<int64_t>(nt, 1));
+      if (n > 0)
+        OVFEM_HIP(hipMemcpyAsync(dw.p, wavelet, (size_t)n * nt * sizeof(double), hipMemcpyHostToDevice, s->stream));
+      OVFEM_HIP(hipStreamSynchronize(s->stream));
+    } catch (...) {
+      st.free();
+      dw.free();
+      throw;
     }
-    OVFEM_HIP(hipStreamSynchronize(s->stream));
-    std::swap(s->src_ptr, dptr);
-    std::swap(s->src_node, dnd);
-    std::swap(s->src_comp, dcp);
-    std::swap(s->src_row, drow);
+    std::swap(s->src, st);
     std::swap(s->wavelet, dw);
-    dptr.free();
-    dnd.free();
-    dcp.free();
-    drow.free();
+    st.free();
     dw.free();
+    s->src_node_h.swap(nd);
+    s->src_comp_h.swap(cp);
+    s->src_shot_h.swap(sh);
     s->n_src = n;
     s->src_nt = n > 0 ? (int)nt : 0;
+    s->invalidate_launches();
   });
 }
 
@@ -556,46 +765,33 @@ ovfem_status ovfem_set_receivers(ovfem_solver* s, int32_t n, const int64_t* node
     require(s != nullptr, "ovfem_set_receivers: solver is NULL");
     require(n >= 0 && nt_max >= 0, "ovfem_set_receivers: negative count");
     require(n == 0 || node, "ovfem_set_receivers: node is NULL");
-    require((double)n * 3.0 * (double)nt_max < 2147483647.0 * 4.0, "ovfem_set_receivers: trace buffer too large");
-    const int nwg = s->geom.n_wg;
-    std::vector<std::vector<int>> per(nwg);
+    require(nt_max < 2147483647 && (double)n * 3.0 * (double)nt_max < 2147483647.0,
+            "ovfem_set_receivers: trace buffer too large");
+    std::vector<int64_t> nd(n);
     for (int i = 0; i < n; ++i) {
       require(node[i] >= 0 && (size_t)node[i] < s->n_nodes, "ovfem_set_receivers: node out of range");
-      const int64_t X = node[i] % (s->nx + 1), Y = (node[i] / (s->nx + 1)) % (s->ny + 1),
-                    Z = node[i] / ((s->nx + 1) * (s->ny + 1));
-      per[s->tile_of(X, Y, Z)].push_back(i);
+      nd[i] = node[i];
     }
-    std::vector<int> ptr(nwg + 1, 0), nd, idx;
-    for (int w = 0; w < nwg; ++w) {
-      ptr[w + 1] = ptr[w] + (int)per[w].size();
-      for (int i : per[w]) {
-        nd.push_back((int)node[i]);
-        idx.push_back(i);
-      }
+    ReceiverTables rt;
+    DevBuf<double> tr;
+    try {
+      rt = s->build_receivers(s->geom, nd);
+      tr.alloc((size_t)s->n_shots * n * 3 * nt_max);
+      OVFEM_HIP(hipMemsetAsync(tr.p, 0, tr.n * sizeof(double), s->stream));
+      OVFEM_HIP(hipStreamSynchronize(s->stream));
+    } catch (...) {
+      rt.free();
+      tr.free();
+      throw;
     }
-    DevBuf<int> dptr, dnd, didx;
-    DevBuf<double> dtr;
-    dptr.alloc(nwg + 1);
-    dnd.alloc(nd.size());
-    didx.alloc(idx.size());
-    dtr.alloc((size_t)s->n_shots * n * 3 * nt_max);
-    OVFEM_HIP(hipMemcpyAsync(dptr.p, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s->stream));
-    if (n > 0) {
-      OVFEM_HIP(hipMemcpyAsync(dnd.p, nd.data(), nd.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(didx.p, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, s->stream));
-    }
-    OVFEM_HIP(hipMemsetAsync(dtr.p, 0, dtr.n * sizeof(double), s->stream));
-    OVFEM_HIP(hipStreamSynchronize(s->stream));
-    std::swap(s->rec_ptr, dptr);
-    std::swap(s->rec_node, dnd);
-    std::swap(s->rec_idx, didx);
-    std::swap(s->traces, dtr);
-    dptr.free();
-    dnd.free();
-    didx.free();
-    dtr.free();
+    std::swap(s->rec, rt);
+    std::swap(s->traces, tr);
+    rt.free();
+    tr.free();
+    s->rec_node_h.swap(nd);
     s->n_rec = n;
     s->rec_nt = (int)nt_max;
+    s->invalidate_launches();
   });
 }
 
@@ -621,18 +817,20 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
     require(s != nullptr, "ovfem_matvec: solver is NULL");
     require(u && Ku, "ovfem_matvec: NULL array");
     require(s->model_set, "ovfem_matvec: model not set", OVFEM_ESTATE);
-    const size_t bytes = 3 * s->n_nodes * sizeof(double);
+    const size_t bytes = s->vec() * sizeof(double);
     const char *a = (const char*)u, *b = (const char*)Ku;
     require(a + bytes <= b || b + bytes <= a, "ovfem_matvec: u and Ku overlap");
     s->check_device();
-    KArgs A = s->base_args();
+    KArgs A = s->shot_args(0, s->cur);
     A.u = u;
     A.ku = Ku;
+    A.src_nt = 0;
+    A.rec_nt = 0;
     if (s->precision != OVFEM_FP64) {
-      s->launch_exponents(u, s->expo_tmp.p);
+      s->launch_exponents(s->geom, u, s->expo_tmp.p, 1);
       A.exp_in = s->expo_tmp.p;
     }
-    s->launch_layer(A, MODE_MATVEC);
+    launch_unit<MODE_MATVEC>(s->precision, A, nullptr, 0, s->stream);
   });
 }
 
@@ -642,7 +840,8 @@ ovfem_status ovfem_get_wavefield(ovfem_solver* s, int32_t which, double* out) {
     require(which == 0 || which == 1, "ovfem_get_wavefield: which must be 0 or 1");
     require(out != nullptr, "ovfem_get_wavefield: out is NULL");
     const int src = which == 0 ? s->cur : s->cur ^ 1;
-    OVFEM_HIP(hipMemcpyAsync(out, s->u[src].p, 3 * s->n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    OVFEM_HIP(hipMemcpyAsync(out, s->u[src].p, (size_t)s->n_shots * s->vec() * sizeof(double),
+                             hipMemcpyDeviceToDevice, s->stream));
     OVFEM_HIP(hipStreamSynchronize(s->stream));
   });
 }
@@ -653,10 +852,10 @@ ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double
     require(un && unm1, "ovfem_set_wavefield: NULL array");
     require(step >= 0, "ovfem_set_wavefield: step < 0");
     s->check_device();
-    const size_t bytes = 3 * s->n_nodes * sizeof(double);
+    const size_t bytes = (size_t)s->n_shots * s->vec() * sizeof(double);
     OVFEM_HIP(hipMemcpyAsync(s->u[s->cur].p, un, bytes, hipMemcpyDeviceToDevice, s->stream));
     OVFEM_HIP(hipMemcpyAsync(s->u[s->cur ^ 1].p, unm1, bytes, hipMemcpyDeviceToDevice, s->stream));
-    s->launch_exponents(s->u[s->cur].p, s->expo[s->exp_cur].p);
+    s->launch_exponents(s->geom, s->u[s->cur].p, s->expo[s->cur].p, s->n_shots);
     s->exp_valid = true;
     s->step = step;
     s->ckpt_valid = false;
@@ -682,16 +881,129 @@ ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step) {
   });
 }
 
+ovfem_status ovfem_set_tuning(ovfem_solver* s, int32_t chunk_planes, int32_t persistent_groups,
+                              int32_t graph_steps) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_set_tuning: solver is NULL");
+    require(chunk_planes >= 1 && chunk_planes <= 4096, "ovfem_set_tuning: chunk_planes must be in 1..4096");
+    require(persistent_groups >= 0, "ovfem_set_tuning: persistent_groups < 0");
+    require(graph_steps >= 0 && graph_steps <= 4096 && graph_steps % 2 == 0,
+            "ovfem_set_tuning: graph_steps must be even and in 0..4096");
+    s->check_device();
+    if (make_geom(s->nx, s->ny, s->nz, chunk_planes).tz != s->geom.tz) s->retile(chunk_planes);
+    s->chunk_planes = chunk_planes;
+    s->persist_groups = persistent_groups;
+    s->graph_steps = graph_steps;
+    s->invalidate_launches();
+  });
+}
+
+ovfem_status ovfem_get_tuning(ovfem_solver* s, int32_t* chunk_planes, int32_t* persistent_groups,
+                              int32_t* graph_steps) {
+  return guarded([&] {
+    require(s != nullptr && chunk_planes && persistent_groups && graph_steps, "ovfem_get_tuning: NULL argument");
+    *chunk_planes = s->chunk_planes;
+    *persistent_groups = s->persist_groups;
+    *graph_steps = s->graph_steps;
+  });
+}
+
+ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_step) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_autotune: solver is NULL");
+    require(steps >= 2 && steps <= 100000, "ovfem_autotune: steps must be in 2..100000");
+    require(s->model_set && s->dt_set, "ovfem_autotune: model and dt not set", OVFEM_ESTATE);
+    s->check_device();
+    const size_t nv = (size_t)s->n_shots * s->vec(), bytes = nv * sizeof(double);
+    DevBuf<double> keep, keep_tr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int64_t step0 = s->step;
+    const int g0 = s->graph_steps;
+    int best_planes = s->chunk_planes, best_persist = s->persist_groups;
+    double best = std::numeric_limits<double>::infinity();
+    auto cleanup = [&] {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      keep.free();
+      keep_tr.free();
+    };
+    try {
+      // the state (wavefield pair, traces, step counter) is saved and restored
+      keep.alloc(2 * nv);
+      keep_tr.alloc(s->traces.n);
+      OVFEM_HIP(hipMemcpyAsync(keep.p, s->u[s->cur].p, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(keep.p + nv, s->u[s->cur ^ 1].p, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(keep_tr.p, s->traces.p, s->traces.n * sizeof(double), hipMemcpyDeviceToDevice,
+                               s->stream));
+      OVFEM_HIP(hipEventCreate(&e0));
+      OVFEM_HIP(hipEventCreate(&e1));
+      std::vector<int> plane_opts = {8, 12, 16, 24, 32};
+      std::vector<int> persist_opts = {0};
+      if (s->n_shots > 1) {
+        hipDeviceProp_t prop;
+        OVFEM_HIP(hipGetDeviceProperties(&prop, s->device));
+        const int cus = std::max(8, prop.multiProcessorCount);
+        persist_opts = {0, 2 * cus, 4 * cus};
+      }
+      s->ckpt_valid = false;
+      s->graph_steps = 0;  // plain launches: the graph only removes launch gaps
+      int last_tz = -1;
+      for (int pl : plane_opts) {
+        const int tz = make_geom(s->nx, s->ny, s->nz, pl).tz;
+        if (tz == last_tz) continue;
+        last_tz = tz;
+        s->retile(pl);
+        for (int pg : persist_opts) {
+          s->persist_groups = pg;
+          s->invalidate_launches();
+          s->do_steps(2);  // warm-up: tables, caches
+          OVFEM_HIP(hipEventRecord(e0, s->stream));
+          s->do_steps(steps);
+          OVFEM_HIP(hipEventRecord(e1, s->stream));
+          OVFEM_HIP(hipEventSynchronize(e1));
+          float ms = 0;
+          OVFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (ms / steps < best) {
+            best = ms / steps;
+            best_planes = pl;
+            best_persist = pg;
+          }
+        }
+      }
+      s->retile(best_planes);
+      s->persist_groups = best_persist;
+      s->graph_steps = g0;
+      s->invalidate_launches();
+      OVFEM_HIP(hipMemcpyAsync(s->u[s->cur].p, keep.p, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(s->u[s->cur ^ 1].p, keep.p + nv, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(s->traces.p, keep_tr.p, s->traces.n * sizeof(double), hipMemcpyDeviceToDevice,
+                               s->stream));
+      s->launch_exponents(s->geom, s->u[s->cur].p, s->expo[s->cur].p, s->n_shots);
+      s->exp_valid = true;
+      s->step = step0;
+      OVFEM_HIP(hipStreamSynchronize(s->stream));
+    } catch (...) {
+      s->graph_steps = g0;
+      (void)hipStreamSynchronize(s->stream);
+      cleanup();
+      throw;
+    }
+    cleanup();
+    if (best_ms_per_step) *best_ms_per_step = best;
+  });
+}
+
 ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max_steps) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_checkpointing: solver is NULL");
     require(every >= 0 && max_steps >= 0, "ovfem_set_checkpointing: negative argument");
+    require(every == 0 || s->n_shots == 1, "ovfem_set_checkpointing: the adjoint needs a one-shot solver");
     s->check_device();
     DevBuf<double> buf;
     int64_t slots = 0;
     if (every > 0) {
       slots = max_steps / every + 1;
-      buf.alloc((size_t)slots * 2 * 3 * s->n_nodes);
+      buf.alloc((size_t)slots * 2 * s->vec());
     }
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     std::swap(s->ckpt, buf);
@@ -709,101 +1021,92 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
     require(residual && g_lam && g_mu, "ovfem_adjoint: NULL array");
     s->check_device();
     const int64_t n = s->step;
-    require(s->ckpt_valid && s->ckpt_every > 0,
+    require(s->ckpt_valid && s->ckpt_every > 0 && s->n_shots == 1,
             "ovfem_adjoint: the forward run since reset was not checkpointed (call ovfem_set_checkpointing, "
-            "then step from reset without changing precision or wavefield)", OVFEM_ESTATE);
+            "then step from reset without changing precision, tiling or wavefield)",
+            OVFEM_ESTATE);
     require(n >= 1, "ovfem_adjoint: no forward steps to differentiate", OVFEM_ESTATE);
     require(s->n_rec > 0 && n <= s->rec_nt, "ovfem_adjoint: receivers must record every forward step", OVFEM_ESTATE);
     require(s->model_set && s->dt_set, "ovfem_adjoint: model and dt not set", OVFEM_ESTATE);
     s->refresh_acoef();
     const int64_t every = s->ckpt_every;
-    const size_t vec = 3 * s->n_nodes;
+    const size_t vec = s->vec();
     const Geom& g = s->geom;
 
-    // adjoint sources: every receiver component, with the residual as its force
-    std::vector<int> rec_node_h(s->n_rec), rec_idx_h(s->n_rec), rec_ptr_h(g.n_wg + 1);
-    OVFEM_HIP(hipMemcpy(rec_node_h.data(), s->rec_node.p, s->n_rec * 4, hipMemcpyDeviceToHost));
-    OVFEM_HIP(hipMemcpy(rec_idx_h.data(), s->rec_idx.p, s->n_rec * 4, hipMemcpyDeviceToHost));
-    OVFEM_HIP(hipMemcpy(rec_ptr_h.data(), s->rec_ptr.p, (g.n_wg + 1) * 4, hipMemcpyDeviceToHost));
+    // adjoint sources: each receiver component, driven by its residual row
+    std::vector<std::vector<int>> per(g.n_wg);
+    for (int r = 0; r < s->n_rec; ++r) per[ovfem_solver::tile_of(g, s->rec_node_h[r])].push_back(r);
     std::vector<int> aptr(g.n_wg + 1, 0), anode, acomp, arow;
     for (int w = 0; w < g.n_wg; ++w) {
-      for (int r = rec_ptr_h[w]; r < rec_ptr_h[w + 1]; ++r)
+      for (int r : per[w])
         for (int c = 0; c < 3; ++c) {
-          anode.push_back(rec_node_h[r]);
+          anode.push_back((int)s->rec_node_h[r]);
           acomp.push_back(c);
-          arow.push_back(3 * rec_idx_h[r] + c);
+          arow.push_back(3 * r + c);
         }
       aptr[w + 1] = (int)anode.size();
     }
-    DevBuf<int> d_aptr, d_anode, d_acomp, d_arow;
-    DevBuf<double> seg, wbuf, zeros;
-    DevBuf<int> fexp, wexp;
-    d_aptr.alloc(aptr.size());
-    d_anode.alloc(anode.size());
-    d_acomp.alloc(acomp.size());
-    d_arow.alloc(arow.size());
-    seg.alloc((size_t)(every + 1) * vec);
-    wbuf.alloc(2 * vec);
-    fexp.alloc(2 * g.n_wg);
-    wexp.alloc(2 * g.n_wg);
+    DevBuf<int> d_aptr, d_anode, d_acomp, d_arow, fexp, wexp;
+    DevBuf<double> seg, wbuf;
     auto free_all = [&] {
-      d_aptr.free(); d_anode.free(); d_acomp.free(); d_arow.free();
-      seg.free(); wbuf.free(); fexp.free(); wexp.free();
+      for (auto* b : {&d_aptr, &d_anode, &d_acomp, &d_arow, &fexp, &wexp}) b->free();
+      seg.free();
+      wbuf.free();
     };
     try {
-      OVFEM_HIP(hipMemcpyAsync(d_aptr.p, aptr.data(), aptr.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(d_anode.p, anode.data(), anode.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(d_acomp.p, acomp.data(), acomp.size() * 4, hipMemcpyHostToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(d_arow.p, arow.data(), arow.size() * 4, hipMemcpyHostToDevice, s->stream));
+      upload(d_aptr, aptr, s->stream);
+      upload(d_anode, anode, s->stream);
+      upload(d_acomp, acomp, s->stream);
+      upload(d_arow, arow, s->stream);
+      seg.alloc((size_t)(every + 1) * vec);
+      wbuf.alloc(2 * vec);
+      fexp.alloc(2 * g.n_wg);
+      wexp.alloc(2 * g.n_wg);
       OVFEM_HIP(hipMemsetAsync(g_lam, 0, s->n_elem * sizeof(double), s->stream));
       OVFEM_HIP(hipMemsetAsync(g_mu, 0, s->n_elem * sizeof(double), s->stream));
       OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 2 * vec * sizeof(double), s->stream));
       double* w[2] = {wbuf.p, wbuf.p + vec};
-      int wc = 0, we = 0;  // w[wc] = w^{m+1}, w[wc ^ 1] = w^{m+2}
-      s->launch_exponents(w[0], wexp.p);
+      int wc = 0;  // w[wc] = w^{m+1}, w[wc ^ 1] = w^{m+2}; half wc of wexp: exponents of w[wc]
+      s->launch_exponents(g, w[0], wexp.p, 1);
 
-      KArgs F = s->base_args();  // forward recompute: forward sources, no receivers
+      KArgs F = s->shot_args(0, s->cur);  // forward recompute: forward sources, no recording
       F.rec_nt = 0;
-      KArgs B = s->base_args();  // adjoint steps: residual injected at the receivers
+      KArgs B = F;  // adjoint steps: the residual injected at the receivers
       B.src_ptr = d_aptr.p;
       B.src_node = d_anode.p;
       B.src_comp = d_acomp.p;
       B.src_row = d_arow.p;
       B.wavelet = residual;
       B.src_nt = s->rec_nt;
-      B.rec_nt = 0;
       const int gblocks = (int)((s->n_elem + NTHR - 1) / NTHR);
 
       for (int64_t sg = (n - 1) / every; sg >= 0; --sg) {
         const int64_t s0 = sg * every, e0 = std::min(s0 + every, n);
-        // state(k) = u^{s0+k}: slot 0 and u^{s0-1} from the checkpoint, the rest recomputed
+        // state(k) = u^{s0+k}: u^{s0} and u^{s0-1} from the checkpoint, the rest recomputed
         auto state = [&](int64_t k) -> double* {
           if (k < 0) return s->ckpt_u(sg, 1);
           if (k == 0) return s->ckpt_u(sg, 0);
           return seg.p + (size_t)k * vec;
         };
         int fe = 0;
-        s->launch_exponents(state(0), fexp.p);
+        s->launch_exponents(g, state(0), fexp.p, 1);
         for (int64_t t = s0; t < e0; ++t) {
           F.u = state(t - s0);
           F.uprev = state(t - s0 - 1);
           F.unext = state(t - s0 + 1);
           F.exp_in = fexp.p + fe * g.n_wg;
           F.exp_out = fexp.p + (fe ^ 1) * g.n_wg;
-          F.step = t;
-          s->launch_layer(F, MODE_STEP);
+          launch_unit<MODE_STEP>(s->precision, F, nullptr, t, s->stream);
           fe ^= 1;
         }
         for (int64_t m = e0; m > s0; --m) {
           B.u = w[wc];
           B.uprev = w[wc ^ 1];
           B.unext = w[wc ^ 1];
-          B.exp_in = wexp.p + we * g.n_wg;
-          B.exp_out = wexp.p + (we ^ 1) * g.n_wg;
-          B.step = m - 1;
-          s->launch_layer(B, MODE_STEP);
+          B.exp_in = wexp.p + wc * g.n_wg;
+          B.exp_out = wexp.p + (wc ^ 1) * g.n_wg;
+          launch_unit<MODE_STEP>(s->precision, B, nullptr, m - 1, s->stream);
           wc ^= 1;
-          we ^= 1;
           ovfem_gradient_kernel<<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc], g_lam,
                                                                  g_mu);
           OVFEM_HIP(hipGetLastError());
@@ -816,6 +1119,77 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       throw;
     }
     free_all();
+  });
+}
+
+ovfem_status ovfem_batch_create(ovfem_batch** out, ovfem_solver* const* members, int32_t n) {
+  return guarded([&] {
+    require(out != nullptr, "ovfem_batch_create: out is NULL");
+    *out = nullptr;
+    require(members != nullptr && n >= 1 && n <= OVFEM_MAX_BATCH, "ovfem_batch_create: member count out of range");
+    for (int i = 0; i < n; ++i) {
+      require(members[i] != nullptr, "ovfem_batch_create: NULL member");
+      require(members[i]->device == members[0]->device, "ovfem_batch_create: members on different devices");
+      require(members[i]->stream == members[0]->stream, "ovfem_batch_create: members on different streams");
+      for (int j = 0; j < i; ++j) require(members[j] != members[i], "ovfem_batch_create: repeated member");
+    }
+    auto b = new ovfem_batch();
+    b->members.assign(members, members + n);
+    b->stream = members[0]->stream;
+    *out = b;
+  });
+}
+
+ovfem_status ovfem_batch_destroy(ovfem_batch* b) {
+  return guarded([&] { delete b; });
+}
+
+ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups) {
+  return guarded([&] {
+    require(b != nullptr, "ovfem_batch_set_tuning: batch is NULL");
+    require(persistent_groups >= 0, "ovfem_batch_set_tuning: persistent_groups < 0");
+    b->persist_groups = persistent_groups;
+  });
+}
+
+ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
+  return guarded([&] {
+    require(b != nullptr, "ovfem_batch_step: batch is NULL");
+    require(n >= 0, "ovfem_batch_step: n < 0");
+    const int precision = b->members[0]->precision;
+    double items = 0;
+    for (auto* m : b->members) {
+      require(m->precision == precision, "ovfem_batch_step: members differ in precision", OVFEM_ESTATE);
+      m->check_device();
+      items += (double)m->n_shots * m->geom.n_wg;
+    }
+    require(items < 2147483647.0, "ovfem_batch_step: too many work items");
+    if (n == 0) return;
+    for (auto* m : b->members) m->prepare_steps();
+    // one unit per shot of each member; table q holds the arguments for the steps of
+    // relative parity q (a member's buffer parity flips with every step)
+    std::vector<KArgs> t;
+    std::vector<int> begin(1, 0);
+    for (int q = 0; q < 2; ++q)
+      for (auto* m : b->members)
+        for (int s = 0; s < m->n_shots; ++s) {
+          KArgs A = m->shot_args(s, m->cur ^ q);
+          A.step = m->step;
+          t.push_back(A);
+          if (q == 0) begin.push_back(begin.back() + m->geom.n_wg);
+        }
+    const int n_units = (int)begin.size() - 1, total = begin.back();
+    OVFEM_HIP(hipStreamSynchronize(b->stream));  // earlier batch launches may read the old tables
+    upload(b->units, t, b->stream);
+    upload(b->begin, begin, b->stream);
+    for (int64_t i = 0; i < n; ++i)
+      launch_units(precision, b->units.p + (size_t)(i & 1) * n_units, b->begin.p, n_units, total, b->persist_groups,
+                   nullptr, i, b->stream);
+    for (auto* m : b->members) {
+      m->cur ^= (int)(n & 1);
+      m->step += n;
+      m->ckpt_valid = false;
+    }
   });
 }
 

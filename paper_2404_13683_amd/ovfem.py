@@ -16,8 +16,8 @@ LIB_PATH = os.path.join(HERE, "libovfem.so")
 
 OVFEM_FP64 = 0
 OVFEM_INT8 = 1
-OVFEM_INT8_I32 = 2
-PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8, "int8-i32": OVFEM_INT8_I32}
+OVFEM_INT8_BF16 = 2
+PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8, "int8-bf16": OVFEM_INT8_BF16}
 
 # name -> (restype, argtypes); mirrors include/ovfem.h
 _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -41,6 +41,13 @@ SIGNATURES = {
     "ovfem_get_step": (_i32, [_vp, ctypes.POINTER(_i64)]),
     "ovfem_set_checkpointing": (_i32, [_vp, _i64, _i64]),
     "ovfem_adjoint": (_i32, [_vp, _vp, _vp, _vp]),
+    "ovfem_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
+    "ovfem_get_tuning": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "ovfem_autotune": (_i32, [_vp, _i32, ctypes.POINTER(_f64)]),
+    "ovfem_batch_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32]),
+    "ovfem_batch_destroy": (_i32, [_vp]),
+    "ovfem_batch_set_tuning": (_i32, [_vp, _i32]),
+    "ovfem_batch_step": (_i32, [_vp, _i64]),
     "ovfem_synchronize": (_i32, [_vp]),
 }
 
@@ -196,15 +203,16 @@ class Solver:
         return out
 
     def get_wavefield(self, which=0, out=None):
+        """u^n (which=0) or u^{n-1} (which=1) of every shot, (n_shots * n_nodes * 3,)."""
         import torch
-        n = 3 * self.n_nodes
+        n = self.n_shots * 3 * self.n_nodes
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device="cuda")
         _check(_LIB.ovfem_get_wavefield(self._h, int(which), _dev_f64(out, n, "out")))
         return out
 
     def set_wavefield(self, un, unm1, step=0):
-        n = 3 * self.n_nodes
+        n = self.n_shots * 3 * self.n_nodes
         _check(_LIB.ovfem_set_wavefield(self._h, _dev_f64(un, n, "un"), _dev_f64(unm1, n, "unm1"), int(step)))
 
     def get_traces(self, out=None):
@@ -235,3 +243,45 @@ class Solver:
         v = ctypes.c_int64()
         _check(_LIB.ovfem_get_step(self._h, ctypes.byref(v)))
         return v.value
+
+    # --- launch configuration
+    def set_tuning(self, chunk_planes=16, persistent_groups=0, graph_steps=64):
+        _check(_LIB.ovfem_set_tuning(self._h, int(chunk_planes), int(persistent_groups), int(graph_steps)))
+
+    def get_tuning(self):
+        a, b, c = _i32(), _i32(), _i32()
+        _check(_LIB.ovfem_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"chunk_planes": a.value, "persistent_groups": b.value, "graph_steps": c.value}
+
+    def autotune(self, steps=20):
+        """Pick the fastest launch configuration; returns its ms per step."""
+        ms = _f64()
+        _check(_LIB.ovfem_autotune(self._h, int(steps), ctypes.byref(ms)))
+        return ms.value
+
+
+class Batch:
+    """Solvers of uneven sizes stepped together, one kernel launch per step."""
+
+    def __init__(self, solvers):
+        self.members = list(solvers)
+        arr = (_vp * len(self.members))(*[m._h.value for m in self.members])
+        self._h = ctypes.c_void_p()
+        _check(_LIB.ovfem_batch_create(ctypes.byref(self._h), arr, len(self.members)))
+
+    def set_tuning(self, persistent_groups=0):
+        _check(_LIB.ovfem_batch_set_tuning(self._h, int(persistent_groups)))
+
+    def step(self, n=1):
+        _check(_LIB.ovfem_batch_step(self._h, int(n)))
+
+    def close(self):
+        if self._h:
+            _check(_LIB.ovfem_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -245,6 +245,104 @@ def adjoint_c4(nx=96, ny=96, nz=96, h=5.0, f0=5.0, nt=1000, n_rec=32, seed=5, pe
     return true, start
 
 
+def fractal_surface(rng, nx, ny, hurst=0.7, relief=40.0):
+    """Seeded fractal height field (nx x ny cell centres), max |height - mean| = relief.
+
+    Spectral synthesis: random phases with amplitude |k|^-(hurst + 1), i.e. the power
+    spectrum |k|^-(2 hurst + 2) of a fractional Brownian surface.
+    """
+    kx = np.fft.fftfreq(nx)[None, :]
+    ky = np.fft.fftfreq(ny)[:, None]
+    k = np.sqrt(kx * kx + ky * ky)
+    k[0, 0] = np.inf
+    amp = k ** -(hurst + 1.0)
+    spec = amp * np.exp(2j * np.pi * rng.random((ny, nx)))
+    z = np.real(np.fft.ifft2(spec))
+    z -= z.mean()
+    return relief * z / np.abs(z).max()
+
+
+def top_solid_nodes(rng, n, solid, margin=1, exclude=()):
+    """n distinct seeded nodes on the top of the solid: node (i, j, kt + 1) above the
+    highest solid voxel kt of column (i, j)."""
+    nz, ny, nx = solid.shape
+    out = []
+    taken = set(int(e) for e in exclude)
+    while len(out) < n:
+        i = int(rng.integers(margin, nx - margin))
+        j = int(rng.integers(margin, ny - margin))
+        col = np.nonzero(solid[:, j, i])[0]
+        if col.size == 0:
+            continue
+        nd = node_id(i, j, col.max() + 1, nx, ny)
+        if nd not in taken:
+            taken.add(nd)
+            out.append(nd)
+    return np.array(out, dtype=np.int64)
+
+
+def topography_c5(nx=512, ny=512, nz=256, h=2.0, f0=5.0, nt=4000, n_rec=8, seed=6, relief=None,
+                  hurst=0.7, vs=(200.0, 600.0, 1500.0), rho=(1800.0, 2100.0, 2500.0)):
+    """Fractal free-surface topography over a nested two-bowl basin in bedrock.
+
+    Default 512 x 512 x 256 voxels, h = 2 m.  Surface: seeded fractal height field
+    (Hurst 0.7) of relief +-40 m (scaled with nz for smaller grids) around a mean
+    elevation 1.25 relief below the top of the box; a voxel is solid if its centre lies
+    below the surface (air voxels removed).  Materials (Vp = 2 Vs): bedrock Vs 1500,
+    rho 2500; a seeded ellipsoidal bowl under the mean surface with Vs 600, rho 2100;
+    inside it a shallower nested bowl with Vs 200, rho 1800.  Air voxels carry bedrock
+    values (unused).  Centre-surface z-force, Ricker f0, 8 seeded receivers on the
+    surface, dt = 0.5 h / max Vp.
+    """
+    rng = np.random.default_rng(seed)
+    if relief is None:
+        relief = 40.0 * nz / 256.0
+    top = nz * h
+    mean_surface = top - 1.25 * relief
+    surf = mean_surface + fractal_surface(rng, nx, ny, hurst, relief)      # (ny, nx)
+    zc = (np.arange(nz) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    xc = (np.arange(nx) + 0.5) * h
+    solid = (zc[:, None, None] < surf[None, :, :]).astype(np.uint8)
+    Lx, Ly = nx * h, ny * h
+    cx, cy = rng.uniform(0.35, 0.65) * Lx, rng.uniform(0.35, 0.65) * Ly
+    ax, ay = rng.uniform(0.2, 0.35) * Lx, rng.uniform(0.2, 0.35) * Ly
+    az = rng.uniform(0.25, 0.4) * mean_surface
+    dx = ((xc - cx) / ax)[None, None, :]
+    dy = ((yc - cy) / ay)[None, :, None]
+    dz = ((mean_surface - zc) / az)[:, None, None]
+    r_outer = dx * dx + dy * dy + dz * dz
+    r_inner = (dx / 0.6) ** 2 + (dy / 0.6) ** 2 + (dz / 0.4) ** 2
+    vs_f = np.full((nz, ny, nx), vs[2])
+    rho_f = np.full((nz, ny, nx), rho[2])
+    outer = (r_outer < 1.0) & (zc[:, None, None] < mean_surface + relief + h)
+    vs_f[outer] = vs[1]
+    rho_f[outer] = rho[1]
+    inner = outer & (r_inner < 1.0)
+    vs_f[inner] = vs[0]
+    rho_f[inner] = rho[0]
+    del r_outer, r_inner, outer, inner
+    lam, mu = lame_from_velocities(2.0 * vs_f, vs_f, rho_f)
+    del vs_f
+    dt = float(0.5 * h / (2.0 * max(vs)))
+    col = np.nonzero(solid[:, ny // 2, nx // 2])[0]
+    src = np.array([node_id(nx // 2, ny // 2, col.max() + 1, nx, ny)], np.int64)
+    rec = top_solid_nodes(rng, n_rec, solid, exclude=src)
+    return Workload("c5-topography", nx, ny, nz, h, lam, mu, rho_f, box_fixed(nx, ny, nz), dt, nt,
+                    src, np.array([2], np.int32), np.array([0], np.int32),
+                    ricker(nt, dt, f0)[None, :], rec, solid=solid,
+                    meta=dict(f0=f0, seed=seed, relief=relief, hurst=hurst))
+
+
+def single_shot(w, shot):
+    """The one-shot workload made of shot `shot` of a multi-shot workload."""
+    import dataclasses
+    sel = np.nonzero(np.asarray(w.src_shot) == shot)[0]
+    return dataclasses.replace(w, name="%s-shot%d" % (w.name, shot), src_node=w.src_node[sel],
+                               src_comp=w.src_comp[sel], src_shot=np.zeros(len(sel), np.int32),
+                               wavelet=w.wavelet[sel], n_shots=1)
+
+
 def random_field(shape, seed, scale=1.0):
     """Seeded standard-normal nodal field (for per-matvec parity)."""
     return scale * np.random.default_rng(seed).standard_normal(shape)

@@ -7,7 +7,7 @@ from paper_2404_13683_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "int8", "int8-i32"]
+PRECS = ["fp64", "int8", "int8-bf16"]
 
 
 def _rel(a, b):

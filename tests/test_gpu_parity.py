@@ -11,7 +11,7 @@ from paper_2404_13683_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "int8", "int8-i32"]
+PRECS = ["fp64", "int8", "int8-bf16"]
 MATVEC_TOL = 1e-12
 TRACE_TOL = 1e-9
 
@@ -129,11 +129,11 @@ def test_int8_not_less_accurate_than_fp64():
                 errs[p].append(abs(float(Fraction(float(got[p][k, j, i, c])) - exact[c])) / abs(float(exact[c])))
     med = {p: float(np.median(errs[p])) for p in PRECS}
     print("median rel error vs exact:", med)
-    for p in ("int8", "int8-i32"):
+    for p in ("int8", "int8-bf16"):
         assert med[p] <= med["fp64"]
         assert max(errs[p]) < 1e-13
     # both matrix-core forms compute identical digit products
-    assert np.array_equal(got["int8"], got["int8-i32"])
+    assert np.array_equal(got["int8"], got["int8-bf16"])
 
 
 @pytest.mark.parametrize("prec", PRECS)

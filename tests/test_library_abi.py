@@ -45,10 +45,23 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert b"positive" in lib.ovfem_last_error()
     assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, -1.0, 1, 0, None) == -1
     assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 1, 7, None) == -1
-    assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 2, 0, None) == -1
+    assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 0, 0, None) == -1
+    assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 4097, 0, None) == -1
+    assert b"n_shots" in lib.ovfem_last_error()
     assert lib.ovfem_step(None, 1) == -1
+    assert lib.ovfem_set_tuning(None, 16, 0, 64) == -1
+    assert lib.ovfem_autotune(None, 10, None) == -1
     assert lib.ovfem_destroy(None) == 0
-    assert lib.ovfem_version() >= 100
+    b = ctypes.c_void_p()
+    assert lib.ovfem_batch_create(None, None, 1) == -1
+    assert lib.ovfem_batch_create(ctypes.byref(b), None, 0) == -1
+    members = (ctypes.c_void_p * 1)(None)
+    assert lib.ovfem_batch_create(ctypes.byref(b), members, 1) == -1
+    assert b"NULL member" in lib.ovfem_last_error()
+    assert lib.ovfem_batch_step(None, 1) == -1
+    assert lib.ovfem_batch_set_tuning(None, 0) == -1
+    assert lib.ovfem_batch_destroy(None) == 0
+    assert lib.ovfem_version() >= 200
 
 
 def test_product_path_does_not_use_the_oracle():
