@@ -13,7 +13,12 @@ DOF-updates per second; the FP64 path, their ratio and the INT8-vs-FP64 receiver
 trace error are reported beside it.  The CPU oracle is timed on a bounded sample
 of the same workload on the host's cores.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Other workloads (parity cases, one JSON line each, not the headline):
+  --workload c3-shots    64 shots on 128 x 128 x 64 in one launch per step
+  --workload c3-uneven   16 layered domains of uneven size, one batched launch per step
+  --workload c5          512 x 512 x 256 fractal topography over a basin, air removed
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload NAME]
 """
 import argparse
 import hashlib
@@ -30,7 +35,6 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF-updates/s/step: INT8-MFMA vs FP64 path at ≤1e-9 trace rel err; % roofline"
 HBM_PEAK = 8.0e12          # bytes/s
 INT8_PEAK = 5.0e15         # dense INT8 MFMA ops/s
-BF16_PEAK = 2.5e15         # dense bf16 MFMA flop/s (the digit products run on bf16 matrix cores)
 FP64_PEAK = 78.6e12        # FP64 vector flop/s
 INT8_OPS_PER_ELEMENT = 2 * 48 * 24 * 8    # [AL; AM] (48 x 24) times 8 digit slices
 FP64_FLOP_PER_ELEMENT = 2 * 2 * 24 * 24   # AL u and AM u in FP64
@@ -81,47 +85,71 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
-def algorithmic_bytes(nx, ny, nz):
-    """Bytes a step must move: u^n, u^{n-1} read, u^{n+1} written, dt^2/m per node; lam, mu per element."""
+def algorithmic_bytes(nx, ny, nz, shots=1):
+    """Bytes a step must move: per shot u^n, u^{n-1} read and u^{n+1} written (72 B per node);
+    once, dt^2/m per node (8 B) and lam, mu per element (16 B)."""
     nodes = (nx + 1) * (ny + 1) * (nz + 1)
-    return 80 * nodes + 16 * nx * ny * nz
+    return 72 * nodes * shots + 8 * nodes + 16 * nx * ny * nz
 
 
-def time_path(wl, prec, warmup, steps):
+def _timed(step, warmup, steps):
+    """HIP events on the current (= the solvers') stream around `steps` steps."""
     import torch
-
-    from paper_2404_13683_amd.ovfem import Solver
-    s = Solver.from_workload(wl, precision=prec, receivers_nt=warmup + steps)
-    s.reset()
-    s.step(warmup)
+    step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    s.step(steps)
+    step(steps)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / max(steps, 1)
+    return e0.elapsed_time(e1) / max(steps, 1)
+
+
+def time_path(wl, prec, warmup, steps, autotune=True):
+    """One solver (all shots of the workload): ms per step and the traces."""
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver.from_workload(wl, precision=prec, receivers_nt=warmup + steps)
+    tuning = None
+    if autotune:
+        s.autotune(steps=10)
+        tuning = s.get_tuning()
+    s.reset()
+    ms = _timed(s.step, warmup, steps)
     traces = s.get_traces().cpu().numpy()
     s.close()
-    return ms, traces
+    return ms, traces, tuning
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """The oracle stepping the same model on the host: whole steps until the budget is spent."""
+def time_batch(wls, prec, warmup, steps):
+    """A batch of solvers of uneven size stepped together."""
+    from paper_2404_13683_amd.ovfem import Batch, Solver
+    sols = [Solver.from_workload(w, precision=prec, receivers_nt=warmup + steps) for w in wls]
+    b = Batch(sols)
+    ms = _timed(b.step, warmup, steps)
+    traces = np.concatenate([s.get_traces().cpu().numpy().ravel() for s in sols])
+    b.close()
+    for s in sols:
+        s.close()
+    return ms, traces, None
+
+
+def cpu_baseline(wl, budget_s=15.0, label=None):
+    """The oracle stepping one shot of the same model on the host until the budget is spent."""
     from oracle import assembly as oasm
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         threads = 1
-    m = oasm.Model(wl.lam, wl.mu, wl.rho, wl.h, wl.fixed, wl.dt)
+    m = oasm.Model(wl.lam, wl.mu, wl.rho, wl.h, wl.fixed, wl.dt, solid=wl.solid)
+    sel = np.asarray(wl.src_shot) == 0
     u = np.zeros(m.node_shape)
     up = np.zeros(m.node_shape)
     n = 0
     t0 = time.perf_counter()
     while True:
-        F = oasm.forcing(m.node_shape, wl.src_node, wl.src_comp, wl.wavelet[:, n])
+        F = oasm.forcing(m.node_shape, wl.src_node[sel], wl.src_comp[sel], wl.wavelet[sel, n % wl.wavelet.shape[1]])
         un = m.step(u, up, F)
         up, u = u, un
         n += 1
@@ -129,17 +157,42 @@ def cpu_baseline(wl, budget_s=15.0):
             break
     dt = time.perf_counter() - t0
     return {"value": wl.free_dof() * n / dt, "unit": "DOF-updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d full steps of the same 256x256x128 workload (numpy FP64 oracle, %.1f s)" % (n, dt)}
+            "sample": "%d full steps of one shot of %s (numpy FP64 oracle, %.1f s)"
+                      % (n, label or wl.name, dt)}
+
+
+def make_workload(name, nt):
+    """(list of workloads, description, batched?) for a workload name."""
+    from paper_2404_13683_amd import workloads
+    if name == "c2":
+        w = workloads.layered_c2(nt=nt)
+        return [w], ("layered-256x256x128 (8.4M voxels, %d free DOF), h=5 m, Ricker 5 Hz, dt=%.4e s"
+                     % (w.free_dof(), w.dt)), False
+    if name == "c3-shots":
+        w = workloads.shots_c3(nt=nt)
+        return [w], ("64 shots on layered-128x128x64 (%d free DOF per shot), h=5 m, one launch per step"
+                     % w.free_dof()), False
+    if name == "c3-uneven":
+        ws = workloads.uneven_domains_c3(nt=nt)
+        return ws, ("16 layered domains 32^3..160x160x80 (%d free DOF in all), one batched launch per step"
+                    % sum(w.free_dof() for w in ws)), True
+    if name == "c5":
+        w = workloads.topography_c5(nt=nt)
+        return [w], ("topography-basin-512x512x256 (67M voxels, %d free DOF, air removed), h=2 m, dt=%.4e s"
+                     % (w.free_dof(), w.dt)), False
+    raise SystemExit("unknown workload %r" % name)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--paths", default="fp64,int8")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3-shots", "c3-uneven", "c5"])
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
     args = ap.parse_args()
     if args.copy_probe:
@@ -151,22 +204,28 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2404_13683_amd import workloads
 
     torch.cuda.set_device(0)
-    wl = workloads.layered_c2(nt=args.warmup + args.steps)
-    free_dof = wl.free_dof()
+    nt = args.warmup + args.steps
+    wls, desc, batched = make_workload(args.workload, nt)
+    free_dof = sum(w.free_dof() * w.n_shots for w in wls)
+    n_elem = sum(w.nx * w.ny * w.nz * w.n_shots for w in wls)
+    bytes_step = sum(algorithmic_bytes(w.nx, w.ny, w.nz, w.n_shots) for w in wls)
     paths = args.paths.split(",")
     res = {}
     for p in paths:
-        ms, tr = time_path(wl, p, args.warmup, args.steps)
-        res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "traces": tr}
-        print("[bench] %s: %.4f ms/step, %.4e DOF-updates/s" % (p, ms, res[p]["value"]), file=sys.stderr, flush=True)
+        if batched:
+            ms, tr, tuning = time_batch(wls, p, args.warmup, args.steps)
+        else:
+            ms, tr, tuning = time_path(wls[0], p, args.warmup, args.steps, autotune=not args.no_autotune)
+        res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "traces": tr, "tuning": tuning}
+        print("[bench] %s %s: %.4f ms/step, %.4e DOF-updates/s, tuning %s"
+              % (args.workload, p, ms, res[p]["value"], tuning), file=sys.stderr, flush=True)
     head = "int8" if "int8" in res else paths[0]
     ms = res[head]["ms_per_step"]
-    n_elem = wl.nx * wl.ny * wl.nz
-    bytes_step = algorithmic_bytes(wl.nx, wl.ny, wl.nz)
     hbm = bytes_step / (ms * 1e-3)
+    sha = kernel_sha()
+    traffic = measured_traffic(head) if args.workload == "c2" else None
     out = {
         "metric": METRIC,
         "value": res[head]["value"],
@@ -178,31 +237,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8-digits(bf16-mfma,exact)+f64" if head == "int8" else "f64",
+        "dtype": "int8-digits(i8-mfma,int32-acc,exact)+f64" if head == "int8" else
+                 ("int8-digits(bf16-mfma,exact)+f64" if head == "int8-bf16" else "f64"),
         "data": "synthetic",
-        "config": {"workload": "layered-256x256x128 (8.4M voxels, %d free DOF), h=5 m, Ricker 5 Hz, dt=%.4e s"
-                               % (free_dof, wl.dt),
-                   "path": head, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz},
+        "config": {"workload": desc, "path": head, "tuning": res[head]["tuning"],
+                   "domains": [[w.nx, w.ny, w.nz, w.n_shots] for w in wls] if len(wls) > 1 else
+                   [wls[0].nx, wls[0].ny, wls[0].nz, wls[0].n_shots]},
         "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": hbm / HBM_PEAK, "traffic": measured_traffic(head), "kernel_sha": kernel_sha(),
+                     "frac": hbm / HBM_PEAK, "traffic": traffic, "kernel_sha": sha,
                      "algorithmic_bytes_per_step": bytes_step,
                      "mfma_frac_int8_peak": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / INT8_PEAK
-                     if head == "int8" else None,
-                     "mfma_frac_bf16_peak": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / BF16_PEAK
-                     if head == "int8" else None},
+                     if head.startswith("int8") else None},
     }
     if "fp64" in res:
         f = res["fp64"]
-        out["fp64_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"], "traffic": measured_traffic("fp64"),
+        out["fp64_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"],
+                            "traffic": measured_traffic("fp64") if args.workload == "c2" else None,
                             "fp64_frac": FP64_FLOP_PER_ELEMENT * n_elem / (f["ms_per_step"] * 1e-3) / FP64_PEAK,
-                            "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK}
-    if "fp64" in res and "int8" in res:
-        a, b = res["int8"]["traces"], res["fp64"]["traces"]
-        out["int8_vs_fp64"] = {"speedup": res["fp64"]["ms_per_step"] / res["int8"]["ms_per_step"],
+                            "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK,
+                            "tuning": f["tuning"]}
+    if "fp64" in res and head != "fp64":
+        a, b = res[head]["traces"], res["fp64"]["traces"]
+        out["int8_vs_fp64"] = {"speedup": res["fp64"]["ms_per_step"] / res[head]["ms_per_step"],
                                "trace_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
-                               "steps_compared": args.warmup + args.steps}
+                               "steps_compared": nt}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_budget, label=desc)
     print(json.dumps(out))
 
 

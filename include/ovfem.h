@@ -181,9 +181,9 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
  * work-group marches through (the tiling is 15 x 15 node columns by about chunk_planes
  * planes; default 16).  persistent_groups (>= 0): for n_shots > 1, cap on the launch
  * grid, rounded down to a multiple of 8 (0 = one work-group per tile and shot).
- * graph_steps (even, 0..4096; default 64): ovfem_step calls of at least that many steps
- * replay a captured HIP graph of graph_steps steps instead of launching each step
- * (0 = never; graphs are not used while checkpointing for the adjoint).  The FP64 path
+ * graph_steps (even, 0..4096; default 0 = never): ovfem_step calls of at least that many
+ * steps replay a captured HIP graph of graph_steps steps instead of launching each step
+ * (graphs are not used while checkpointing for the adjoint).  The FP64 path
  * gives bitwise-identical results under every setting; the INT8 forms take their
  * per-tile exponents over the tiling, so chunk_planes can change their last bits (their
  * accuracy bound does not change).  Keeps the wavefield state; a changed tiling
@@ -197,8 +197,8 @@ ovfem_status ovfem_get_tuning(ovfem_solver* s, int32_t* chunk_planes, int32_t* p
 
 /* Autotuner: times `steps` (2..100000) plain-launch steps of the solver's own model,
  * sources and precision for each candidate chunk depth (8, 12, 16, 24, 32 planes) and,
- * for n_shots > 1, grid caps of 0, 2 and 4 work-groups per compute unit, and keeps the
- * fastest (graph_steps unchanged).  The wavefield pair, traces and step counter are
+ * for n_shots > 1, grid caps of 0, 2 and 4 work-groups per compute unit, keeps the
+ * fastest, then times graph_steps 0 and 64 at that setting and keeps the faster.  The wavefield pair, traces and step counter are
  * restored afterwards; a checkpointed forward run is invalidated.  best_ms_per_step
  * (HOST, nullable) receives the best time per step in milliseconds.  Synchronises the
  * stream.  ESTATE without model and dt. */

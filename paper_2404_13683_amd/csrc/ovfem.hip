@@ -259,7 +259,7 @@ struct ovfem_solver {
   int ckpt_precision = OVFEM_FP64;
 
   // launch configuration
-  int chunk_planes = 16, persist_groups = 0, graph_steps = 64;
+  int chunk_planes = 16, persist_groups = 0, graph_steps = 0;
   DevBuf<KArgs> units;           // [parity][shot]: arguments of each shot, u^n in buffer parity
   DevBuf<int> unit_begin;        // [shot + 1]: first work item of each shot
   DevBuf<long long> step_base;   // step index of the next replay of a captured block
@@ -946,7 +946,7 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
         persist_opts = {0, 2 * cus, 4 * cus};
       }
       s->ckpt_valid = false;
-      s->graph_steps = 0;  // plain launches: the graph only removes launch gaps
+      s->graph_steps = 0;  // plain launches for the tiling and grid choice
       int last_tz = -1;
       for (int pl : plane_opts) {
         const int tz = make_geom(s->nx, s->ny, s->nz, pl).tz;
@@ -972,7 +972,27 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       }
       s->retile(best_planes);
       s->persist_groups = best_persist;
-      s->graph_steps = g0;
+      // captured blocks against plain launches, at the chosen tiling
+      const int64_t gsteps = std::max<int64_t>(64, ((int64_t)steps + 63) / 64 * 64);
+      double best_graph = std::numeric_limits<double>::infinity();
+      int best_gs = 0;
+      for (int gs : {0, 64}) {
+        s->graph_steps = gs;
+        s->invalidate_launches();
+        s->do_steps(gs > 0 ? gs : 2);  // warm-up; captures the block
+        OVFEM_HIP(hipEventRecord(e0, s->stream));
+        s->do_steps(gsteps);
+        OVFEM_HIP(hipEventRecord(e1, s->stream));
+        OVFEM_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        OVFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / gsteps < best_graph) {
+          best_graph = ms / gsteps;
+          best_gs = gs;
+        }
+      }
+      best = std::min(best, best_graph);
+      s->graph_steps = best_gs;
       s->invalidate_launches();
       OVFEM_HIP(hipMemcpyAsync(s->u[s->cur].p, keep.p, bytes, hipMemcpyDeviceToDevice, s->stream));
       OVFEM_HIP(hipMemcpyAsync(s->u[s->cur ^ 1].p, keep.p + nv, bytes, hipMemcpyDeviceToDevice, s->stream));

@@ -245,7 +245,7 @@ class Solver:
         return v.value
 
     # --- launch configuration
-    def set_tuning(self, chunk_planes=16, persistent_groups=0, graph_steps=64):
+    def set_tuning(self, chunk_planes=16, persistent_groups=0, graph_steps=0):
         _check(_LIB.ovfem_set_tuning(self._h, int(chunk_planes), int(persistent_groups), int(graph_steps)))
 
     def get_tuning(self):

@@ -163,7 +163,7 @@ def test_autotune_keeps_state_and_results(n_shots):
     assert ms > 0.0
     _same(_state(s), before)
     t = s.get_tuning()
-    assert t["chunk_planes"] in (8, 12, 16, 24, 32) and t["graph_steps"] == 64
+    assert t["chunk_planes"] in (8, 12, 16, 24, 32) and t["graph_steps"] in (0, 64)
     s.step(w.nt - 25)
     _same(_state(s), _state(ref))
 
