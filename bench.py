@@ -106,14 +106,15 @@ def _timed(step, warmup, steps):
     return e0.elapsed_time(e1) / max(steps, 1)
 
 
-def time_path(wl, prec, warmup, steps, autotune=True):
+def time_path(wl, prec, warmup, steps, autotune=True, chunk_planes=0):
     """One solver (all shots of the workload): ms per step and the traces."""
     from paper_2404_13683_amd.ovfem import Solver
     s = Solver.from_workload(wl, precision=prec, receivers_nt=warmup + steps)
-    tuning = None
-    if autotune:
+    if chunk_planes:
+        s.set_tuning(chunk_planes=chunk_planes)
+    elif autotune:
         s.autotune(steps=10)
-        tuning = s.get_tuning()
+    tuning = s.get_tuning()
     s.reset()
     ms = _timed(s.step, warmup, steps)
     traces = s.get_traces().cpu().numpy()
@@ -193,6 +194,7 @@ def main():
     ap.add_argument("--paths", default="fp64,int8")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3-shots", "c3-uneven", "c5"])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--chunk-planes", type=int, default=0, help="fixed z-chunk depth instead of autotuning")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
     args = ap.parse_args()
     if args.copy_probe:
@@ -217,7 +219,8 @@ def main():
         if batched:
             ms, tr, tuning = time_batch(wls, p, args.warmup, args.steps)
         else:
-            ms, tr, tuning = time_path(wls[0], p, args.warmup, args.steps, autotune=not args.no_autotune)
+            ms, tr, tuning = time_path(wls[0], p, args.warmup, args.steps, autotune=not args.no_autotune,
+                                       chunk_planes=args.chunk_planes)
         res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "traces": tr, "tuning": tuning}
         print("[bench] %s %s: %.4f ms/step, %.4e DOF-updates/s, tuning %s"
               % (args.workload, p, ms, res[p]["value"], tuning), file=sys.stderr, flush=True)
