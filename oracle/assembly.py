@@ -14,6 +14,14 @@ What is computed, all in float64:
     Sec. 3, Eq. (19) with the force sign of Eq. (3)):
         u^{n+1} = 2 u^n - u^{n-1} + dt^2 m^{-1} (F^n - K u^n)   on free DOFs,
     fixed DOFs (and nodes with no mass) held at zero;
+  * optional Rayleigh damping C = alpha M + beta K (the paper's experiment uses it,
+    Sec. 3; its time discretization is not printed).  Reading: the mass-proportional
+    velocity is centred and the stiffness-proportional one taken backward, which keeps
+    the step explicit with one K product:
+        M (u^{n+1} - 2u^n + u^{n-1}) / dt^2 + alpha M (u^{n+1} - u^{n-1}) / (2 dt)
+          + beta K (u^n - u^{n-1}) / dt + K u^n = F^n,
+    i.e. (1 + alpha dt/2) u^{n+1} = 2u^n - (1 - alpha dt/2) u^{n-1}
+          + dt^2 m^{-1} (F^n - K (u^n + (beta/dt) (u^n - u^{n-1})));
   * receivers record u^{n+1} after step n;
   * discrete energy, discrete adjoint of a trace misfit, and the error measure of
     Sec. 3, Eq. (18).
@@ -86,10 +94,18 @@ def forcing(shape, src_node, src_comp, amp):
     return F
 
 
+def rayleigh_coefficients(zeta, f1, f2):
+    """(alpha, beta) of Rayleigh damping C = alpha M + beta K with damping ratio zeta at
+    the frequencies f1 and f2: a mode of angular frequency w is damped with ratio
+    alpha / (2 w) + beta w / 2, which equals zeta at w1 = 2 pi f1 and w2 = 2 pi f2."""
+    w1, w2 = 2.0 * np.pi * f1, 2.0 * np.pi * f2
+    return 2.0 * zeta * w1 * w2 / (w1 + w2), 2.0 * zeta / (w1 + w2)
+
+
 class Model:
     """Inputs of one simulation, plus the oracle's own derived mass."""
 
-    def __init__(self, lam, mu, rho, h, fixed, dt, solid=None):
+    def __init__(self, lam, mu, rho, h, fixed, dt, solid=None, alpha=0.0, beta=0.0):
         self.lam = np.asarray(lam, dtype=np.float64)
         self.mu = np.asarray(mu, dtype=np.float64)
         self.rho = np.asarray(rho, dtype=np.float64)
@@ -106,13 +122,20 @@ class Model:
         # dt^2 / m on free nodes, 0 elsewhere
         self.a = np.zeros(self.node_shape[:3])
         self.a[self.free] = self.dt ** 2 / self.mass[self.free]
+        self.alpha = float(alpha)
+        self.beta = float(beta)
 
     def K(self, u):
         return matvec(u, self.lam, self.mu, self.h)
 
     def step(self, u, u_prev, F):
         """One central-difference step; returns u^{n+1}."""
-        un = 2.0 * u - u_prev + self.a[..., None] * (F - self.K(u))
+        if self.alpha == 0.0 and self.beta == 0.0:
+            un = 2.0 * u - u_prev + self.a[..., None] * (F - self.K(u))
+        else:
+            ad = 0.5 * self.alpha * self.dt
+            w = u + (self.beta / self.dt) * (u - u_prev)
+            un = (2.0 * u - (1.0 - ad) * u_prev + self.a[..., None] * (F - self.K(w))) / (1.0 + ad)
         un[~self.free] = 0.0
         return un
 
