@@ -106,10 +106,12 @@ def _timed(step, warmup, steps):
     return e0.elapsed_time(e1) / max(steps, 1)
 
 
-def time_path(wl, prec, warmup, steps, autotune=True, chunk_planes=0):
+def time_path(wl, prec, warmup, steps, autotune=True, chunk_planes=0, stages=8):
     """One solver (all shots of the workload): ms per step and the traces."""
     from paper_2404_13683_amd.ovfem import Solver
     s = Solver.from_workload(wl, precision=prec, receivers_nt=warmup + steps)
+    if prec == "int8":
+        s.set_stages(stages)
     if chunk_planes:
         s.set_tuning(chunk_planes=chunk_planes)
     elif autotune:
@@ -195,6 +197,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3-shots", "c3-uneven", "c5"])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--chunk-planes", type=int, default=0, help="fixed z-chunk depth instead of autotuning")
+    ap.add_argument("--stage-sweep", action="store_true",
+                    help="also time the INT8 path with 4..7 digit stages (accuracy/speed trade, Table 3)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
     args = ap.parse_args()
     if args.copy_probe:
@@ -264,6 +268,17 @@ def main():
         out["int8_vs_fp64"] = {"speedup": res["fp64"]["ms_per_step"] / res[head]["ms_per_step"],
                                "trace_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
                                "steps_compared": nt}
+    if args.stage_sweep and not batched and "fp64" in res:
+        sweep = []
+        for M in (4, 5, 6, 7):
+            ms_m, tr_m, tun_m = time_path(wls[0], "int8", args.warmup, args.steps,
+                                          autotune=not args.no_autotune, chunk_planes=args.chunk_planes, stages=M)
+            b = res["fp64"]["traces"]
+            sweep.append({"stages": M, "ms_per_step": ms_m, "value": free_dof / (ms_m * 1e-3),
+                          "trace_rel_l2_vs_fp64": float(np.linalg.norm(tr_m - b) / np.linalg.norm(b)),
+                          "tuning": tun_m})
+            print("[bench] stages %d: %.4f ms/step" % (M, ms_m), file=sys.stderr, flush=True)
+        out["stage_sweep"] = sweep
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_budget, label=desc)
     print(json.dumps(out))

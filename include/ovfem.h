@@ -88,7 +88,8 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
 /* Free every device buffer of the solver (waits for its stream).  NULL is accepted. */
 ovfem_status ovfem_destroy(ovfem_solver* s);
 
-/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_BF16). */
+/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_BF16).
+ * EINVAL for OVFEM_INT8_BF16 while the stage count (ovfem_set_stages) is not 8. */
 ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision);
 
 /* Per-element material, HOST arrays of nx*ny*nz float64: Lame lam, shear modulus mu,
@@ -106,7 +107,8 @@ ovfem_status ovfem_set_fixed_nodes(ovfem_solver* s, const uint8_t* fixed);
 
 /* Time step dt (> 0).  EINVAL if dt exceeds the element-wise stability bound
  * 2 / sqrt(max eigenvalue of K_e / (rho_e h^3 / 8)) over solid voxels, which bounds
- * the central-difference limit of the assembled system from below. */
+ * the central-difference limit of the assembled system from below (with Rayleigh
+ * damping, the bound of ovfem_set_damping). */
 ovfem_status ovfem_set_dt(ovfem_solver* s, double dt);
 
 /* Point forces, HOST arrays: n sources at nodes node[i] (flat node id), component
@@ -177,6 +179,32 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
  * Synchronises the stream.  ESTATE if the preconditions do not hold. */
 ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_lam, double* g_mu);
 
+/* Rayleigh damping C = alpha M + beta K (alpha, beta >= 0; both 0 = undamped, the
+ * default).  The paper's experiment (Sec. 3) uses Rayleigh damping without printing its
+ * time discretization; the step taken here centres the mass-proportional velocity and
+ * takes the stiffness-proportional one backward, so it stays explicit with one K
+ * product:
+ *     (1 + alpha dt/2) u^{n+1} = 2 u^n - (1 - alpha dt/2) u^{n-1}
+ *                               + dt^2 M^{-1} (F^n - K (u^n + (beta/dt)(u^n - u^{n-1}))).
+ * Its stability bound on dt shrinks to w_max^2 dt (dt + 2 beta) <= 4 (checked against
+ * the element bound of w_max, as ovfem_set_dt does).  A damped solver keeps a third
+ * nodal vector per shot, does not replay captured graphs, and has no adjoint (ESTATE);
+ * damped and undamped solvers cannot share a batch.  Resets the wavefield.  EINVAL for
+ * negative or non-finite values, or a dt already set that the new beta makes unstable. */
+ovfem_status ovfem_set_damping(ovfem_solver* s, double alpha, double beta);
+
+/* Digit stages M (4..8, default 8) of OVFEM_INT8: u is split under the tile exponent E
+ * into q = floor(u 2^(8M-2-E)), |q| < 2^(8M-2), written as M balanced base-256 digits
+ * (Sec. 2, Eqs. (16)-(17); the paper's Table 3 compares stage counts).  Fewer stages
+ * mean fewer matrix-core products and recombination steps at lower accuracy: about
+ * 8M - 2 bits relative to the largest value of the 27 neighbouring tiles (M = 4 is
+ * about FP32, M = 8 at least FP64).  OVFEM_INT8_BF16 runs M = 8 only (EINVAL otherwise);
+ * OVFEM_FP64 ignores the setting. */
+ovfem_status ovfem_set_stages(ovfem_solver* s, int32_t stages);
+
+/* Current digit stage count (HOST out-pointer). */
+ovfem_status ovfem_get_stages(ovfem_solver* s, int32_t* stages);
+
 /* Launch configuration.  chunk_planes (1..4096): depth, in node planes, of the z-chunk a
  * work-group marches through (the tiling is 15 x 15 node columns by about chunk_planes
  * planes; default 16).  persistent_groups (>= 0): for n_shots > 1, cap on the launch
@@ -219,7 +247,7 @@ ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups);
 
 /* Enqueue n >= 0 steps of every member (asynchronous).  Each member advances exactly as
  * ovfem_step(member, n) would (bitwise: the same kernels on the same tiles), from its
- * own step counter.  Members must share one precision and have model and dt set
+ * own step counter.  Members must share one precision (and stage count) and have model and dt set
  * (ESTATE otherwise).  Invalidates the members' checkpointed forward runs. */
 ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n);
 

@@ -8,33 +8,34 @@
 // plane k+1 in registers for the next layer, and forms the in-plane sums of the
 // contributions to plane k.  Plane k is then complete (element layers k-1 and k) and
 // the central-difference update of Sec. 2, Eq. (3) runs for it at once:
-//     u^{n+1} = 2 u^n - u^{n-1} + dt^2 m^{-1} (F^n - (K u^n))   (zero where m^{-1} = 0).
-// Every node is summed by one thread in a fixed order: results are bitwise
-// reproducible (no atomics).  Lanes of a wave map to rows of 16 elements along x, so
-// the two in-row neighbours of a node are combined with one DPP row shift.
+//     u^{n+1} = 2 u^n - u^{n-1} + dt^2 m^{-1} (F^n - (K u^n))   (zero where m^{-1} = 0),
+// or its Rayleigh-damped form (DAMP kernels; see KArgs).  Every owned node is updated
+// by one thread; the in-plane sums are formed in LDS with a fixed set of addends per
+// entry (a store, then at most one add of a second term: two-term sums commute
+// exactly), so results are bitwise reproducible.  No global atomics.
 //
 // Element products, K_e u_e = h lam_e K_lam u_e + h mu_e K_mu u_e with the integer
 // matrices AL = 256 K_lam, AM = 128 K_mu (refmat.hpp):
 //   * FP64 path: one thread per element, dense 24 x 24 products in FP64 with the
 //     integer matrices as compile-time constants (the paper's "OVFEM FP64").
 //   * INT8 paths (Sec. 2, Eqs. (10)-(17), reworked for CDNA4).  u is written as
-//     2^(E-62) q, q = floor(u 2^(62-E)) an integer with |q| <= 2^62, under one
+//     2^(E-QB) q, q = floor(u 2^(QB-E)) an integer with |q| < 2^QB, under one
 //     power-of-two exponent E per tile (the paper scales each element by s_e; a
-//     shared exponent lets a node's slices be computed once for its 8 elements, and
-//     the 62 bits keep every value within 2^9 of the tile maximum exact).  q is split
-//     into M = 8 balanced base-256 digits d_j in [-128, 127] (the paper: 8
-//     sign-magnitude base-128 digits of a 56-bit integer), and the digit products with
-//     the 48 x 24 integer matrix [AL; AM] run on the matrix cores, digits taken
-//     pairwise from the top.  PATH_INT8 uses v_mfma_i32_16x16x32_i8:
+//     shared exponent lets a node's slices be computed once for its 8 elements).
+//     q is split into M balanced base-256 digits d_j in [-128, 127], QB = 8M - 2
+//     (M = 8 by default: 62 bits, every value within 2^9 of the tile maximum exact; the
+//     paper: 8 sign-magnitude base-128 digits of a 56-bit integer), and the digit
+//     products with the 48 x 24 integer matrix [AL; AM] run on the matrix cores, digits
+//     taken pairwise from the top.  PATH_INT8 uses v_mfma_i32_16x16x32_i8:
 //     C = A d_hi, C <<= 8, C += A d_lo, exact in INT32 since
 //     |C| <= 384 * 128 * 257 < 2^31 (the paper flushes INT32 every 3 stages).
-//     PATH_BF16 uses v_mfma_f32_16x16x32_bf16 with A (256 d_hi) + A (d_lo + 128) in
-//     one FP32 accumulator: every operand is an integer of at most 8 significant
+//     PATH_BF16 (M = 8) uses v_mfma_f32_16x16x32_bf16 with A (256 d_hi) + A (d_lo + 128)
+//     in one FP32 accumulator: every operand is an integer of at most 8 significant
 //     bits (exact in bf16) and every partial sum an integer below
 //     384 * 128 * 256 + 384 * 255 < 2^24 (exact in FP32); the +128 bias drops out
 //     because each row of K sums to zero (rigid translations).  Both give the same
 //     pair sums, which are recombined in FP64 (Horner with factor 2^16) and scaled by
-//     h lam_e / 256 * 2^(E-62) and h mu_e / 128 * 2^(E-62).
+//     h lam_e / 256 * 2^(E-QB) and h mu_e / 128 * 2^(E-QB).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,10 +56,19 @@ constexpr int NODE_DW = 16;   // dwords of one staged node: 4 pairs x (hi, lo) x
 // lane (its element's nodes x and x+1 in one row) is 16 contiguous bytes
 constexpr int DPLANE = PN * PN * NODE_DW;  // dwords per staged digit plane
 constexpr int DROW = NPAIR * 2 * PN * 2;   // dwords per staged digit row
-// i8 form: [row q][digit j][column x] one dword (c0, c1, c2, 0) of signed digits
-constexpr int NDIG = 2 * NPAIR;
-constexpr int DROW8 = NDIG * PN;
-constexpr int DPLANE8 = PN * DROW8;
+// i8 form with M digits (stages): [row q][digit j][column x] one dword (c0, c1, c2, 0)
+// of signed digits.  Rows are padded to 16 (mod 64) dwords and planes to 32 (mod 64),
+// so the four 16-lane groups of a B-operand read (two tile rows, two planes) and the
+// four 16-thread rows of a staging write fall on disjoint LDS banks.
+constexpr int pad_to(int n, int r) { return n + ((r - n % 64) + 64) % 64; }
+template <int M>
+struct Stages {
+  static_assert(M >= 4 && M <= 8, "4 to 8 digit stages");
+  static constexpr int QB = 8 * M - 2;         // fraction bits of q: |q| < 2^QB
+  static constexpr int NG = (M + 1) / 2;       // digit groups (pairs; the top one single if M is odd)
+  static constexpr int ROW = pad_to(M * PN, 16);
+  static constexpr int PLANE = pad_to(PN * ROW, 32);
+};
 constexpr int FPLANE = 3 * PN * PN;        // doubles per staged FP64 plane
 constexpr int NEXTRA = PN * PN - NTHR;     // staged nodes beyond one per thread (33)
 constexpr int EXP_NONE = -1000000;         // exponent of an all-zero tile
@@ -108,6 +118,13 @@ struct KArgs {
   double* traces;         // [rec][3][rec_nt]
   int src_nt, rec_nt;
   long long step;         // batch launches: the unit's step offset
+  // Rayleigh damping (DAMP kernels only): the product is K w with
+  // w = u^n + damp_b (u^n - u^{n-1}), damp_b = beta / dt, and
+  // u^{n+1} = damp_c1 u^n - damp_c2 u^{n-1} + acoef (F - K w), with
+  // damp_c1 = 2 / (1 + alpha dt / 2), damp_c2 = (1 - alpha dt / 2) / (1 + alpha dt / 2) and
+  // acoef = dt^2 / (m (1 + alpha dt / 2)).  unext must then not alias uprev (the halo
+  // of u^{n-1} is read by neighbouring work-groups).
+  double damp_b, damp_c1, damp_c2;
 };
 
 // Logical tile of this work-group.  Work-groups are dealt to the 8 XCDs round-robin
@@ -215,13 +232,23 @@ __device__ inline void stage_digits(const D3& u, int E, uint32_t* dst) {
     }
 }
 
-// i8 form of the node staging: per digit j the word (d_j(c0), d_j(c1), d_j(c2), 0) of
-// signed digits, written at dst[j * PN] (dst = the node's column in its row).
+// i8 form of the node staging with M digits: q = floor(u 2^(8M-2-E)), |q| < 2^(8M-2),
+// written as M balanced base-256 digits (the bytes of q + sum_j 128 * 256^j, minus 128;
+// the bytes above M are then exactly 128); per digit j the word
+// (d_j(c0), d_j(c1), d_j(c2), 0) is written at dst[j * PN].
+template <int M>
 __device__ inline void stage_digits_i8(const D3& u, int E, uint32_t* dst) {
+  constexpr int QB = Stages<M>::QB;
   uint32_t lo[3], hi[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double x = ldexp(u.v[c], QBITS - E);
+    const double x = ldexp(u.v[c], QB - E);
+    if constexpr (M <= 4) {
+      const int q = (int)floor(x);  // |q| < 2^30
+      lo[c] = ((uint32_t)q + 0x80808080u) ^ 0x80808080u;
+      hi[c] = 0u;
+      continue;
+    }
     const double hd = floor(x * 0x1p-32);
     const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);
     const uint64_t q = ((uint64_t)(uint32_t)(int)hd << 32) | lo_u;
@@ -230,7 +257,7 @@ __device__ inline void stage_digits_i8(const D3& u, int E, uint32_t* dst) {
     hi[c] = (uint32_t)(d >> 32) ^ 0x80808080u;
   }
 #pragma unroll
-  for (int j = 0; j < NDIG; ++j) {
+  for (int j = 0; j < M; ++j) {
     const uint32_t* s = j < 4 ? lo : hi;
     const int sel = j & 3;
     // bytes: c0 byte sel, c1 byte sel, c2 byte sel, 0
@@ -289,8 +316,13 @@ __device__ inline void write_tile_exponent(double local_max, int* dst, double* r
 }
 
 // One work-group tile (tile index wg of its unit) of one time step (or one matvec).
-template <int PATH, int MODE>
+// M: digit stages of PATH_INT8 (the other paths take M = 8).  DAMP: Rayleigh-damped
+// step (MODE_STEP only).
+template <int PATH, int MODE, int M, bool DAMP = false>
 __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const long long step) {
+  static_assert(!DAMP || MODE == MODE_STEP, "damping applies to time steps");
+  using St = Stages<M>;
+  constexpr int QB = PATH == PATH_INT8 ? St::QB : QBITS;
   const Geom g = A.g;
   const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
   const int x0 = tx * TN, y0 = ty * TN, z0 = tzc * g.tz;
@@ -303,7 +335,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
   __shared__ double red[4];
   __shared__ __attribute__((aligned(16))) double matl[PATH == PATH_FP64 ? 2 : 2 * NTHR];  // slices: [b][a] material
-  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * DPLANE8 * 4);
+  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * St::PLANE * 4);
   __shared__ __attribute__((aligned(16))) unsigned char ring_raw[RING_BYTES];
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
@@ -346,6 +378,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   const size_t plane_bytes = (size_t)24 * (g.nx + 1) * (g.ny + 1);
   const size_t layer_bytes = (size_t)16 * g.nx * g.ny;
   const unsigned char* u_base = reinterpret_cast<const unsigned char*>(A.u);
+  const unsigned char* up_base = reinterpret_cast<const unsigned char*>(A.uprev);
   const unsigned char* mat_base = reinterpret_cast<const unsigned char*>(A.mat);
 
   D3 u_main_next, u_extra_next = {{0.0, 0.0, 0.0}};
@@ -368,6 +401,20 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     const unsigned char* plane = u_base + (size_t)(z_ok ? Z : 0) * plane_bytes;
     u_main_next = load_node(plane, main_ref, z_ok);
     if (has_extra) u_extra_next = load_node(plane, extra_ref, z_ok);
+    if constexpr (DAMP) {
+      // stage w = u^n + b (u^n - u^{n-1}); the owned nodes' u^n is reloaded in the
+      // node phase
+      const unsigned char* pplane = up_base + (size_t)(z_ok ? Z : 0) * plane_bytes;
+      const D3 pm = load_node(pplane, main_ref, z_ok);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u_main_next.v[c] = fma(A.damp_b, u_main_next.v[c] - pm.v[c], u_main_next.v[c]);
+      if (has_extra) {
+        const D3 px = load_node(pplane, extra_ref, z_ok);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          u_extra_next.v[c] = fma(A.damp_b, u_extra_next.v[c] - px.v[c], u_extra_next.v[c]);
+      }
+    }
   };
   auto fetch_mat = [&](int k) {
     const bool z_ok = k >= 0 && k < g.nz;
@@ -386,9 +433,9 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       stage_digits(u_main_next, E, P + mq * DROW + 2 * mp);
       if (has_extra) stage_digits(u_extra_next, E, P + xq * DROW + 2 * xp);
     } else {
-      uint32_t* P = ringd + slot * DPLANE8;
-      stage_digits_i8(u_main_next, E, P + mq * DROW8 + mp);
-      if (has_extra) stage_digits_i8(u_extra_next, E, P + xq * DROW8 + xp);
+      uint32_t* P = ringd + slot * St::PLANE;
+      stage_digits_i8<M>(u_main_next, E, P + mq * St::ROW + mp);
+      if (has_extra) stage_digits_i8<M>(u_extra_next, E, P + xq * St::ROW + xp);
     }
   };
 
@@ -420,6 +467,12 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       up[0] = pp[0];
       up[1] = pp[1];
       up[2] = pp[2];
+      if constexpr (DAMP) {
+        const double* pu = reinterpret_cast<const double*>(u_base + node_off);
+        u_own_bot.v[0] = pu[0];
+        u_own_bot.v[1] = pu[1];
+        u_own_bot.v[2] = pu[2];
+      }
       ac = *reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.acoef) +
                                             (size_t)k * (plane_bytes / 3) + main_ref.off / 3);
     }
@@ -456,7 +509,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       for (int i = 0; i < 12; ++i) top_f[i] = y[12 + i];
     } else {
       const int ja = lane & 15, G = lane >> 4;  // element column; lane group
-      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_BF16 ? DPLANE : DPLANE8);
+      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_BF16 ? DPLANE : St::PLANE);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int b = 4 * wave + tt;
@@ -464,8 +517,9 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
         if (layer_ok) {
           const double2 me = *reinterpret_cast<const double2*>(matl + 2 * (b * TE + ja));
           double R[12];
+          constexpr int NGRP = PATH == PATH_INT8 ? St::NG : NPAIR;
 #pragma unroll
-          for (int p = NPAIR - 1; p >= 0; --p) {
+          for (int p = NGRP - 1; p >= 0; --p) {
             if constexpr (PATH == PATH_BF16) {
               // the lane's eight K slots: (c0, c1, c2, 0) of node ja, then of node ja+1
               const uint32_t* P = Pin + (b + (G & 1)) * DROW + 2 * ja;
@@ -484,7 +538,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
               c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag[2], Bl, c2, 0, 0, 0);
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                if (p == NPAIR - 1) {
+                if (p == NGRP - 1) {
                   R[r] = (double)c0[r];
                   R[4 + r] = (double)c1[r];
                   R[8 + r] = (double)c2[r];
@@ -495,23 +549,28 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
                 }
               }
             } else {
-              // digit words of node ja and ja+1 for digits 2p+1 (hi) and 2p (lo)
-              const uint32_t* P = Pin + (b + (G & 1)) * DROW8 + ja;
-              const long Bh = (long)((uint64_t)P[(2 * p + 1) * PN] | ((uint64_t)P[(2 * p + 1) * PN + 1] << 32));
+              // digit words of node ja and ja+1 for digits 2p+1 (hi, absent in the top
+              // group when M is odd) and 2p (lo)
+              const uint32_t* P = Pin + (b + (G & 1)) * St::ROW + ja;
               const long Bl = (long)((uint64_t)P[(2 * p) * PN] | ((uint64_t)P[(2 * p) * PN + 1] << 32));
               const v4i z = {0, 0, 0, 0};
-              v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[0], Bh, z, 0, 0, 0);
-              v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[1], Bh, z, 0, 0, 0);
-              v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[2], Bh, z, 0, 0, 0);
-              c0 = c0 << 8;
-              c1 = c1 << 8;
-              c2 = c2 << 8;
+              v4i c0 = z, c1 = z, c2 = z;
+              if (2 * p + 1 < M) {
+                const long Bh =
+                    (long)((uint64_t)P[(2 * p + 1) * PN] | ((uint64_t)P[(2 * p + 1) * PN + 1] << 32));
+                c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[0], Bh, z, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[1], Bh, z, 0, 0, 0);
+                c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[2], Bh, z, 0, 0, 0);
+                c0 = c0 << 8;
+                c1 = c1 << 8;
+                c2 = c2 << 8;
+              }
               c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[0], Bl, c0, 0, 0, 0);
               c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[1], Bl, c1, 0, 0, 0);
               c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a_frag8[2], Bl, c2, 0, 0, 0);
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                if (p == NPAIR - 1) {
+                if (p == NGRP - 1) {
                   R[r] = (double)c0[r];
                   R[4 + r] = (double)c1[r];
                   R[8 + r] = (double)c2[r];
@@ -525,7 +584,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
           }
           // output s = 4 * row tile + reg: s < 6 rows of AL, s >= 6 rows of AM;
           // dk = (s % 6) / 3, c = s % 3, at corner G + 4 dk
-          const double sl = ldexp(me.x, E - QBITS), sm = ldexp(me.y, E - QBITS);
+          const double sl = ldexp(me.x, E - QB), sm = ldexp(me.y, E - QB);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             ybot[c] = R[c] * sl + R[6 + c] * sm;
@@ -579,14 +638,27 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
             F[2] += sc == 2 ? w : 0.0;
           }
         double un[3];
+        if constexpr (DAMP) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          un[c] = ac > 0.0 ? 2.0 * u_own_bot.v[c] - up[c] + ac * (F[c] - f[c]) : 0.0;
+          for (int c = 0; c < 3; ++c)
+            un[c] = ac > 0.0 ? A.damp_c1 * u_own_bot.v[c] - A.damp_c2 * up[c] + ac * (F[c] - f[c]) : 0.0;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            un[c] = ac > 0.0 ? 2.0 * u_own_bot.v[c] - up[c] + ac * (F[c] - f[c]) : 0.0;
+        }
         double* o = A.unext + 3 * nid;
         o[0] = un[0];
         o[1] = un[1];
         o[2] = un[2];
-        tile_max = fmax(tile_max, fmax(fabs(un[0]), fmax(fabs(un[1]), fabs(un[2]))));
+        if constexpr (DAMP) {
+          // the next step stages w^{n+1} = u^{n+1} + b (u^{n+1} - u^n): its tile maximum
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            tile_max = fmax(tile_max, fabs(fma(A.damp_b, un[c] - u_own_bot.v[c], un[c])));
+        } else {
+          tile_max = fmax(tile_max, fmax(fabs(un[0]), fmax(fabs(un[1]), fabs(un[2]))));
+        }
         for (int r = rec_lo; r < rec_hi; ++r)
           if (A.rec_node[r] == (int)nid && step < A.rec_nt) {
             double* tr = A.traces + (long long)A.rec_idx[r] * 3 * A.rec_nt + step;
@@ -603,11 +675,11 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 // One unit (one shot of one grid): one work-group per tile.  The step index is
 // *step_base + step (step_base may be null), so a captured sequence of launches can
 // be replayed with a step base kept in device memory.
-template <int PATH, int MODE>
+template <int PATH, int MODE, int M = 8, bool DAMP = false>
 __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
     ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
-  layer_tile<PATH, MODE>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
+  layer_tile<PATH, MODE, M, DAMP>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
 }
 
 // Many units in one launch (the shots of a grid, or grids of uneven size): unit u owns
@@ -615,7 +687,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
 // gets a contiguous run; a grid smaller than the work list strides over it (the grid
 // size is then a multiple of 8, so a work-group stays on one XCD's run).  The unit's
 // own step offset is units[u].step.
-template <int PATH, int MODE>
+template <int PATH, int MODE, int M = 8, bool DAMP = false>
 __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
     ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                        const long long* step_base, long long step) {
@@ -629,7 +701,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
       else hi = mid - 1;
     }
     const KArgs A = units[lo];
-    layer_tile<PATH, MODE>(A, item - unit_begin[lo], s + A.step);
+    layer_tile<PATH, MODE, M, DAMP>(A, item - unit_begin[lo], s + A.step);
     __syncthreads();  // LDS is reused by the next work item
   }
 }
@@ -639,8 +711,10 @@ __global__ void ovfem_advance_step_kernel(long long* step_base, long long n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
 }
 
-// Tile exponents of an arbitrary nodal vector (same tiling as the stepper).
-__global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const double* u, int* exp_out) {
+// Tile exponents of a nodal vector u, or with up of u + b (u - up) (the vector a damped
+// step stages), in the stepper's tiling.
+__global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const double* u, const double* up, double b,
+                                                               int* exp_out) {
   __shared__ double red[4];
   const int wg = blockIdx.x;
   const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
@@ -650,8 +724,15 @@ __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const doub
   double m = 0.0;
   if (ta < TN && tb < TN && X <= g.nx && Y <= g.ny)
     for (int Z = z0; Z < z1; ++Z) {
-      const double* p = u + 3 * ((long long)X + (long long)(g.nx + 1) * ((long long)Y + (long long)(g.ny + 1) * Z));
-      m = fmax(m, fmax(fabs(p[0]), fmax(fabs(p[1]), fabs(p[2]))));
+      const long long o = 3 * ((long long)X + (long long)(g.nx + 1) * ((long long)Y + (long long)(g.ny + 1) * Z));
+      const double* p = u + o;
+      if (up) {
+        const double* q = up + o;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m = fmax(m, fabs(fma(b, p[c] - q[c], p[c])));
+      } else {
+        m = fmax(m, fmax(fabs(p[0]), fmax(fabs(p[1]), fabs(p[2]))));
+      }
     }
   write_tile_exponent(m, exp_out + wg, red);
 }

@@ -153,32 +153,73 @@ std::vector<uint64_t> make_alane_i8() {
 
 bool valid_precision(int p) { return p == OVFEM_FP64 || p == OVFEM_INT8 || p == OVFEM_INT8_BF16; }
 
+// Element-product form: precision and, for OVFEM_INT8, the digit stage count.
+struct Form {
+  int precision;
+  int stages;
+  bool damp;  // Rayleigh-damped step kernels
+};
+
 // One unit, one work-group per tile.
-template <int MODE>
-void launch_unit(int precision, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
+template <int MODE, bool D>
+void launch_unit_form(Form f, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
   const dim3 grid(A.g.n_wg), block(NTHR);
-  if (precision == OVFEM_FP64)
-    ovfem_layer_kernel<PATH_FP64, MODE><<<grid, block, 0, stream>>>(A, base, step);
-  else if (precision == OVFEM_INT8)
-    ovfem_layer_kernel<PATH_INT8, MODE><<<grid, block, 0, stream>>>(A, base, step);
-  else
-    ovfem_layer_kernel<PATH_BF16, MODE><<<grid, block, 0, stream>>>(A, base, step);
+  if (f.precision == OVFEM_FP64) {
+    ovfem_layer_kernel<PATH_FP64, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
+  } else if (f.precision == OVFEM_INT8) {
+    switch (f.stages) {
+      case 4: ovfem_layer_kernel<PATH_INT8, MODE, 4, D><<<grid, block, 0, stream>>>(A, base, step); break;
+      case 5: ovfem_layer_kernel<PATH_INT8, MODE, 5, D><<<grid, block, 0, stream>>>(A, base, step); break;
+      case 6: ovfem_layer_kernel<PATH_INT8, MODE, 6, D><<<grid, block, 0, stream>>>(A, base, step); break;
+      case 7: ovfem_layer_kernel<PATH_INT8, MODE, 7, D><<<grid, block, 0, stream>>>(A, base, step); break;
+      default: ovfem_layer_kernel<PATH_INT8, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step); break;
+    }
+  } else {
+    ovfem_layer_kernel<PATH_BF16, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
+  }
+}
+template <int MODE>
+void launch_unit(Form f, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
+  if constexpr (MODE == MODE_STEP) {
+    if (f.damp)
+      launch_unit_form<MODE_STEP, true>(f, A, base, step, stream);
+    else
+      launch_unit_form<MODE_STEP, false>(f, A, base, step, stream);
+  } else {
+    launch_unit_form<MODE, false>(f, A, base, step, stream);
+  }
   OVFEM_HIP(hipGetLastError());
 }
 
 // Many units in one launch; grid_cap > 0 caps the grid (rounded down to a multiple of
 // 8, at least 8) so that the work-groups stride over the work list.
-void launch_units(int precision, const KArgs* units, const int* begin, int n_units, int total, int grid_cap,
+template <bool D>
+void launch_units_form(Form f, dim3 g, const KArgs* units, const int* begin, int n_units, int total,
+                       const long long* base, long long step, hipStream_t stream) {
+  const dim3 block(NTHR);
+  const auto U = units;
+  if (f.precision == OVFEM_FP64) {
+    ovfem_batch_kernel<PATH_FP64, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
+  } else if (f.precision == OVFEM_INT8) {
+    switch (f.stages) {
+      case 4: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 4, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
+      case 5: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 5, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
+      case 6: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 6, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
+      case 7: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 7, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
+      default: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
+    }
+  } else {
+    ovfem_batch_kernel<PATH_BF16, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
+  }
+}
+void launch_units(Form f, const KArgs* units, const int* begin, int n_units, int total, int grid_cap,
                   const long long* base, long long step, hipStream_t stream) {
   int grid = total;
   if (grid_cap > 0 && grid_cap < total) grid = std::max(8, (grid_cap / 8) * 8);
-  const dim3 g(grid), block(NTHR);
-  if (precision == OVFEM_FP64)
-    ovfem_batch_kernel<PATH_FP64, MODE_STEP><<<g, block, 0, stream>>>(units, begin, n_units, total, base, step);
-  else if (precision == OVFEM_INT8)
-    ovfem_batch_kernel<PATH_INT8, MODE_STEP><<<g, block, 0, stream>>>(units, begin, n_units, total, base, step);
+  if (f.damp)
+    launch_units_form<true>(f, dim3(grid), units, begin, n_units, total, base, step, stream);
   else
-    ovfem_batch_kernel<PATH_BF16, MODE_STEP><<<g, block, 0, stream>>>(units, begin, n_units, total, base, step);
+    launch_units_form<false>(f, dim3(grid), units, begin, n_units, total, base, step, stream);
   OVFEM_HIP(hipGetLastError());
 }
 
@@ -222,15 +263,20 @@ struct ovfem_solver {
   double h = 0;
   int n_shots = 1;
   int precision = OVFEM_FP64;
+  int stages = 8;  // digit stages M of OVFEM_INT8
   Geom geom{};
   size_t n_nodes = 0, n_elem = 0;
 
-  // state: u[cur] = u^n and u[cur ^ 1] = u^{n-1}, [shot][node][3]; expo[cur] holds the
-  // tile exponents of u^n, [shot][tile]
-  DevBuf<double> u[2];
-  DevBuf<int> expo[2];
-  int cur = 0;
+  // state, [shot][node][3] per buffer: at phase ph, u^n is u[buf_cur(ph)] and u^{n-1} is
+  // u[buf_prev(ph)]; a step writes u^{n+1} into u[buf_next(ph)] and moves to phase
+  // buf_next(ph).  Undamped: two buffers, u^{n+1} over u^{n-1}.  Damped: three
+  // (neighbouring work-groups still read the halo of u^{n-1}).  expo[b] holds the tile
+  // exponents of the staged vector of buffer b (u^n, or w^n when damped), [shot][tile].
+  DevBuf<double> u[3];
+  DevBuf<int> expo[3];
+  int phase = 0;
   bool exp_valid = false;
+  double alpha = 0.0, beta = 0.0;  // Rayleigh damping C = alpha M + beta K
   DevBuf<int> expo_tmp;          // exponents of a matvec operand
   DevBuf<double> mat, acoef;     // mat: [element][2] = (h lam / 256, h mu / 128)
   DevBuf<uint32_t> alane_bf16;
@@ -249,29 +295,29 @@ struct ovfem_solver {
   std::vector<double> mass;      // nodal mass (host)
   std::vector<uint8_t> fixed;    // nodal fixed flags (host)
   bool model_set = false, dt_set = false, acoef_dirty = true;
-  double dt = 0, dt_bound = 0;
+  double dt = 0, wmax2 = 0;      // wmax2: upper bound of the squared angular frequencies
   int64_t step = 0;
 
   // adjoint: forward checkpoints (u^s, u^{s-1}) at s = 0, every, 2 every, ... since reset
   int64_t ckpt_every = 0, ckpt_slots = 0;
   DevBuf<double> ckpt;           // [slot][2][3 n_nodes]
-  bool ckpt_valid = false;       // the run since reset was checkpointed with this precision
-  int ckpt_precision = OVFEM_FP64;
+  bool ckpt_valid = false;       // the run since reset was checkpointed with this form
+  int ckpt_form = -1;
 
   // launch configuration
   int chunk_planes = 16, persist_groups = 0, graph_steps = 0;
-  DevBuf<KArgs> units;           // [parity][shot]: arguments of each shot, u^n in buffer parity
+  DevBuf<KArgs> units;           // [phase][shot]: arguments of each shot at each phase
   DevBuf<int> unit_begin;        // [shot + 1]: first work item of each shot
   DevBuf<long long> step_base;   // step index of the next replay of a captured block
   bool tables_dirty = true;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};  // captured block starting from u[parity]
-  int graph_precision[2] = {-1, -1};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // captured block starting at phase p (undamped)
+  int graph_form[2] = {-1, -1};                   // precision * 16 + stages it was captured with
 
   ~ovfem_solver() {
     (void)hipStreamSynchronize(stream);
     drop_graphs();
-    for (auto* b : {&u[0], &u[1], &mat, &acoef, &wavelet, &traces, &ckpt}) b->free();
-    for (auto* b : {&expo[0], &expo[1], &expo_tmp, &unit_begin}) b->free();
+    for (auto* b : {&u[0], &u[1], &u[2], &mat, &acoef, &wavelet, &traces, &ckpt}) b->free();
+    for (auto* b : {&expo[0], &expo[1], &expo[2], &expo_tmp, &unit_begin}) b->free();
     src.free();
     rec.free();
     alane_bf16.free();
@@ -281,6 +327,19 @@ struct ovfem_solver {
   }
 
   size_t vec() const { return 3 * n_nodes; }
+  bool damped() const { return alpha != 0.0 || beta != 0.0; }
+  int n_phase() const { return damped() ? 3 : 2; }
+  int buf_cur(int ph) const { return ph; }
+  int buf_prev(int ph) const { return damped() ? (ph + 2) % 3 : ph ^ 1; }
+  int buf_next(int ph) const { return damped() ? (ph + 1) % 3 : ph ^ 1; }
+  Form form() const { return Form{precision, stages, damped()}; }
+  int form_code() const { return precision * 16 + (precision == OVFEM_INT8 ? stages : 0); }
+  double damp_b() const { return beta / dt; }
+  double damp_a() const { return 0.5 * alpha * dt; }
+  // stability of the (damped) recursion for the largest mode: w^2 dt (dt + 2 beta) <= 4
+  double dt_limit(double b) const {
+    return wmax2 > 0 ? -b + std::sqrt(b * b + 4.0 / wmax2) : std::numeric_limits<double>::infinity();
+  }
   double* ckpt_u(int64_t slot, int which) { return ckpt.p + (size_t)(2 * slot + which) * vec(); }
 
   void check_device() {
@@ -293,7 +352,7 @@ struct ovfem_solver {
     for (int p = 0; p < 2; ++p) {
       if (graph[p]) (void)hipGraphExecDestroy(graph[p]);
       graph[p] = nullptr;
-      graph_precision[p] = -1;
+      graph_form[p] = -1;
     }
   }
   // launch arguments changed (pointers, tiling, sources, receivers)
@@ -311,18 +370,35 @@ struct ovfem_solver {
   void refresh_acoef() {
     if (!acoef_dirty) return;
     std::vector<double> a(n_nodes, 0.0);
+    const double scale = 1.0 / (1.0 + damp_a());
     for (size_t i = 0; i < n_nodes; ++i)
-      if (!fixed[i] && mass[i] > 0.0) a[i] = dt * dt / mass[i];
+      if (!fixed[i] && mass[i] > 0.0) a[i] = dt * dt / mass[i] * scale;
     OVFEM_HIP(hipMemcpyAsync(acoef.p, a.data(), n_nodes * sizeof(double), hipMemcpyHostToDevice, stream));
     OVFEM_HIP(hipStreamSynchronize(stream));
     acoef_dirty = false;
   }
 
-  void launch_exponents(const Geom& g, const double* v, int* dst, int shots) {
+  // tile exponents of v (or, with vp, of v + b (v - vp)) for every shot
+  void launch_exponents(const Geom& g, const double* v, int* dst, int shots, const double* vp = nullptr,
+                        double b = 0.0) {
     for (int s = 0; s < shots; ++s) {
-      ovfem_exponent_kernel<<<g.n_wg, NTHR, 0, stream>>>(g, v + (size_t)s * vec(), dst + (size_t)s * g.n_wg);
+      ovfem_exponent_kernel<<<g.n_wg, NTHR, 0, stream>>>(g, v + (size_t)s * vec(), vp ? vp + (size_t)s * vec() : nullptr,
+                                                          b, dst + (size_t)s * g.n_wg);
       OVFEM_HIP(hipGetLastError());
     }
+  }
+  // exponents of the vector the next step stages
+  void state_exponents() {
+    if (damped() && !dt_set) {  // the staged vector depends on beta / dt
+      exp_valid = false;
+      return;
+    }
+    const int c = buf_cur(phase), p = buf_prev(phase);
+    if (damped())
+      launch_exponents(geom, u[c].p, expo[c].p, n_shots, u[p].p, damp_b());
+    else
+      launch_exponents(geom, u[c].p, expo[c].p, n_shots);
+    exp_valid = true;
   }
 
   // source lists of every (shot, tile) for tiling g; rows index the wavelet table
@@ -383,17 +459,24 @@ struct ovfem_solver {
     return t;
   }
 
-  // the arguments of one shot with u^n in buffer `parity`
-  KArgs shot_args(int shot, int parity) const {
+  // the arguments of one shot at phase ph
+  KArgs shot_args(int shot, int ph) const {
     KArgs A{};
+    const int c = buf_cur(ph), p = buf_prev(ph), x = buf_next(ph);
     A.g = geom;
-    A.u = u[parity].p + (size_t)shot * vec();
-    A.uprev = u[parity ^ 1].p + (size_t)shot * vec();
-    A.unext = u[parity ^ 1].p + (size_t)shot * vec();
+    A.u = u[c].p + (size_t)shot * vec();
+    A.uprev = u[p].p + (size_t)shot * vec();
+    A.unext = u[x].p + (size_t)shot * vec();
     A.mat = mat.p;
     A.acoef = acoef.p;
-    A.exp_in = expo[parity].p + (size_t)shot * geom.n_wg;
-    A.exp_out = expo[parity ^ 1].p + (size_t)shot * geom.n_wg;
+    A.exp_in = expo[c].p + (size_t)shot * geom.n_wg;
+    A.exp_out = expo[x].p + (size_t)shot * geom.n_wg;
+    if (damped()) {
+      const double ad = damp_a();
+      A.damp_b = damp_b();
+      A.damp_c1 = 2.0 / (1.0 + ad);
+      A.damp_c2 = (1.0 - ad) / (1.0 + ad);
+    }
     A.alane = reinterpret_cast<const v4u*>(alane_bf16.p);
     A.alane8 = alane_i8.p;
     A.src_ptr = src.ptr.p + (size_t)shot * (geom.n_wg + 1);
@@ -413,8 +496,8 @@ struct ovfem_solver {
 
   void refresh_tables() {
     if (!tables_dirty) return;
-    std::vector<KArgs> t((size_t)2 * n_shots);
-    for (int p = 0; p < 2; ++p)
+    std::vector<KArgs> t((size_t)n_phase() * n_shots);
+    for (int p = 0; p < n_phase(); ++p)
       for (int s = 0; s < n_shots; ++s) t[(size_t)p * n_shots + s] = shot_args(s, p);
     std::vector<int> begin(n_shots + 1);
     for (int s = 0; s <= n_shots; ++s) begin[s] = s * geom.n_wg;
@@ -425,17 +508,17 @@ struct ovfem_solver {
     tables_dirty = false;
   }
 
-  // one step of every shot with u^n in buffer `parity`; step index *base + step_arg
-  void launch_step(hipStream_t st, int parity, const long long* base, long long step_arg) {
+  // one step of every shot at phase ph; step index *base + step_arg
+  void launch_step(hipStream_t st, int ph, const long long* base, long long step_arg) {
     if (n_shots == 1)
-      launch_unit<MODE_STEP>(precision, shot_args(0, parity), base, step_arg, st);
+      launch_unit<MODE_STEP>(form(), shot_args(0, ph), base, step_arg, st);
     else
-      launch_units(precision, units.p + (size_t)parity * n_shots, unit_begin.p, n_shots, n_shots * geom.n_wg,
+      launch_units(form(), units.p + (size_t)ph * n_shots, unit_begin.p, n_shots, n_shots * geom.n_wg,
                    persist_groups, base, step_arg, st);
   }
 
-  // capture graph_steps (even) steps starting from buffer parity p, followed by the
-  // advance of the device step base; the parity is p again after the block
+  // capture graph_steps (even) undamped steps starting at phase p, followed by the
+  // advance of the device step base; the phase is p again after the block
   void capture_graph(int p) {
     hipStream_t cs = nullptr;
     hipGraph_t g = nullptr;
@@ -452,7 +535,7 @@ struct ovfem_solver {
       }
       OVFEM_HIP(hipStreamEndCapture(cs, &g));
       OVFEM_HIP(hipGraphInstantiate(&graph[p], g, nullptr, nullptr, 0));
-      graph_precision[p] = precision;
+      graph_form[p] = form_code();
     } catch (...) {
       if (g) (void)hipGraphDestroy(g);
       (void)hipStreamDestroy(cs);
@@ -464,57 +547,53 @@ struct ovfem_solver {
 
   void zero_state() {
     const size_t bytes = (size_t)n_shots * vec() * sizeof(double);
-    OVFEM_HIP(hipMemsetAsync(u[0].p, 0, bytes, stream));
-    OVFEM_HIP(hipMemsetAsync(u[1].p, 0, bytes, stream));
+    for (auto& b : u)
+      if (b.p) OVFEM_HIP(hipMemsetAsync(b.p, 0, bytes, stream));
     if (traces.p) OVFEM_HIP(hipMemsetAsync(traces.p, 0, traces.n * sizeof(double), stream));
-    cur = 0;
+    phase = 0;
     step = 0;
-    launch_exponents(geom, u[cur].p, expo[cur].p, n_shots);
-    exp_valid = true;
+    state_exponents();
     ckpt_valid = ckpt_every > 0;
-    ckpt_precision = precision;
+    ckpt_form = form_code();
   }
 
   void prepare_steps() {
     require(model_set, "ovfem_step: model not set", OVFEM_ESTATE);
     require(dt_set, "ovfem_step: dt not set", OVFEM_ESTATE);
     refresh_acoef();
-    if (!exp_valid) {
-      launch_exponents(geom, u[cur].p, expo[cur].p, n_shots);
-      exp_valid = true;
-    }
+    if (!exp_valid) state_exponents();
     refresh_tables();
   }
 
   void do_steps(int64_t n) {
     prepare_steps();
-    if (ckpt_valid && precision != ckpt_precision) ckpt_valid = false;
+    if (ckpt_valid && form_code() != ckpt_form) ckpt_valid = false;
     int64_t done = 0;
-    if (graph_steps > 0 && !ckpt_valid && n >= graph_steps) {
-      if (!graph[cur] || graph_precision[cur] != precision) {
-        if (graph[cur]) (void)hipGraphExecDestroy(graph[cur]);
-        graph[cur] = nullptr;
-        capture_graph(cur);
+    if (graph_steps > 0 && !ckpt_valid && !damped() && n >= graph_steps) {
+      if (!graph[phase] || graph_form[phase] != form_code()) {
+        if (graph[phase]) (void)hipGraphExecDestroy(graph[phase]);
+        graph[phase] = nullptr;
+        capture_graph(phase);
       }
       const long long s0 = step;
       OVFEM_HIP(hipMemcpyAsync(step_base.p, &s0, sizeof(long long), hipMemcpyHostToDevice, stream));
       OVFEM_HIP(hipStreamSynchronize(stream));  // s0 is a host stack value
-      for (; done + graph_steps <= n; done += graph_steps) OVFEM_HIP(hipGraphLaunch(graph[cur], stream));
-      step += done;  // an even count: cur is unchanged
+      for (; done + graph_steps <= n; done += graph_steps) OVFEM_HIP(hipGraphLaunch(graph[phase], stream));
+      step += done;  // an even count: the phase is unchanged
     }
     for (; done < n; ++done) {
       if (ckpt_valid && step % ckpt_every == 0) {
         const int64_t slot = step / ckpt_every;
         if (slot < ckpt_slots) {
           const size_t bytes = vec() * sizeof(double);
-          OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 0), u[cur].p, bytes, hipMemcpyDeviceToDevice, stream));
-          OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 1), u[cur ^ 1].p, bytes, hipMemcpyDeviceToDevice, stream));
+          OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 0), u[buf_cur(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
+          OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 1), u[buf_prev(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
         } else {
           ckpt_valid = false;  // ran past the checkpoint capacity
         }
       }
-      launch_step(stream, cur, nullptr, step);
-      cur ^= 1;
+      launch_step(stream, phase, nullptr, step);
+      phase = buf_next(phase);
       ++step;
     }
   }
@@ -522,17 +601,18 @@ struct ovfem_solver {
   // change the z-chunk depth: new tiling, tile lists and exponents; the state is kept
   void retile(int planes) {
     const Geom g = make_geom(nx, ny, nz, planes);
-    DevBuf<int> e0, e1, et;
+    DevBuf<int> e0, e1, e2, et;
     SourceTables st;
     ReceiverTables rt;
     try {
       e0.alloc((size_t)n_shots * g.n_wg);
       e1.alloc((size_t)n_shots * g.n_wg);
+      if (u[2].p) e2.alloc((size_t)n_shots * g.n_wg);
       et.alloc(g.n_wg);
       st = build_sources(g, src_node_h, src_comp_h, src_shot_h);
       rt = build_receivers(g, rec_node_h);
     } catch (...) {
-      for (auto* b : {&e0, &e1, &et}) b->free();
+      for (auto* b : {&e0, &e1, &e2, &et}) b->free();
       st.free();
       rt.free();
       throw;
@@ -540,16 +620,16 @@ struct ovfem_solver {
     OVFEM_HIP(hipStreamSynchronize(stream));
     std::swap(expo[0], e0);
     std::swap(expo[1], e1);
+    std::swap(expo[2], e2);
     std::swap(expo_tmp, et);
     std::swap(src, st);
     std::swap(rec, rt);
-    for (auto* b : {&e0, &e1, &et}) b->free();
+    for (auto* b : {&e0, &e1, &e2, &et}) b->free();
     st.free();
     rt.free();
     geom = g;
     chunk_planes = planes;
-    launch_exponents(geom, u[cur].p, expo[cur].p, n_shots);
-    exp_valid = true;
+    state_exponents();
     ckpt_valid = false;  // the INT8 exponent granularity follows the tiling
     invalidate_launches();
     OVFEM_HIP(hipStreamSynchronize(stream));
@@ -560,7 +640,7 @@ struct ovfem_batch {
   std::vector<ovfem_solver*> members;
   hipStream_t stream = nullptr;
   int persist_groups = 0;
-  DevBuf<KArgs> units;  // [relative parity][unit]
+  DevBuf<KArgs> units;  // [relative step mod 6][unit]
   DevBuf<int> begin;    // [unit + 1]
   ~ovfem_batch() {
     (void)hipStreamSynchronize(stream);
@@ -634,6 +714,8 @@ ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_precision: solver is NULL");
     require(valid_precision(precision), "ovfem_set_precision: unknown precision");
+    require(precision != OVFEM_INT8_BF16 || s->stages == 8,
+            "ovfem_set_precision: OVFEM_INT8_BF16 runs 8 digit stages only (call ovfem_set_stages(s, 8) first)");
     s->precision = precision;
   });
 }
@@ -681,14 +763,14 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
               for (int di = 0; di < 2; ++di)
                 mass[(size_t)((i + di) + (nx + 1) * ((j + dj) + (ny + 1) * (k + dk)))] += me;
         }
-    s->dt_bound = wmax2 > 0 ? 2.0 / std::sqrt(wmax2) : std::numeric_limits<double>::infinity();
+    s->wmax2 = wmax2;
     OVFEM_HIP(hipStreamSynchronize(s->stream));  // earlier steps may still read mat
     OVFEM_HIP(hipMemcpyAsync(s->mat.p, mt.data(), 2 * ne * sizeof(double), hipMemcpyHostToDevice, s->stream));
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     s->mass.swap(mass);
     s->model_set = true;
     s->acoef_dirty = true;
-    if (s->dt_set && s->dt > s->dt_bound) s->dt_set = false;  // dt must be set again
+    if (s->dt_set && s->dt > s->dt_limit(s->beta)) s->dt_set = false;  // dt must be set again
     s->zero_state();
   });
 }
@@ -709,11 +791,14 @@ ovfem_status ovfem_set_dt(ovfem_solver* s, double dt) {
     require(s != nullptr, "ovfem_set_dt: solver is NULL");
     require(s->model_set, "ovfem_set_dt: set the model first", OVFEM_ESTATE);
     require(std::isfinite(dt) && dt > 0, "ovfem_set_dt: dt must be positive");
-    require(dt <= s->dt_bound, "ovfem_set_dt: dt = " + std::to_string(dt) +
-                                   " exceeds the element stability bound " + std::to_string(s->dt_bound));
+    const double lim = s->dt_limit(s->beta);
+    require(dt <= lim, "ovfem_set_dt: dt = " + std::to_string(dt) + " exceeds the element stability bound " +
+                           std::to_string(lim) + (s->beta > 0 ? " (with the stiffness-proportional damping)" : ""));
     s->dt = dt;
     s->dt_set = true;
     s->acoef_dirty = true;
+    s->invalidate_launches();  // the damping coefficients depend on dt
+    s->exp_valid = s->exp_valid && !s->damped();
   });
 }
 
@@ -821,7 +906,7 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
     const char *a = (const char*)u, *b = (const char*)Ku;
     require(a + bytes <= b || b + bytes <= a, "ovfem_matvec: u and Ku overlap");
     s->check_device();
-    KArgs A = s->shot_args(0, s->cur);
+    KArgs A = s->shot_args(0, s->phase);
     A.u = u;
     A.ku = Ku;
     A.src_nt = 0;
@@ -830,7 +915,7 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
       s->launch_exponents(s->geom, u, s->expo_tmp.p, 1);
       A.exp_in = s->expo_tmp.p;
     }
-    launch_unit<MODE_MATVEC>(s->precision, A, nullptr, 0, s->stream);
+    launch_unit<MODE_MATVEC>(s->form(), A, nullptr, 0, s->stream);
   });
 }
 
@@ -839,7 +924,7 @@ ovfem_status ovfem_get_wavefield(ovfem_solver* s, int32_t which, double* out) {
     require(s != nullptr, "ovfem_get_wavefield: solver is NULL");
     require(which == 0 || which == 1, "ovfem_get_wavefield: which must be 0 or 1");
     require(out != nullptr, "ovfem_get_wavefield: out is NULL");
-    const int src = which == 0 ? s->cur : s->cur ^ 1;
+    const int src = which == 0 ? s->buf_cur(s->phase) : s->buf_prev(s->phase);
     OVFEM_HIP(hipMemcpyAsync(out, s->u[src].p, (size_t)s->n_shots * s->vec() * sizeof(double),
                              hipMemcpyDeviceToDevice, s->stream));
     OVFEM_HIP(hipStreamSynchronize(s->stream));
@@ -853,10 +938,9 @@ ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double
     require(step >= 0, "ovfem_set_wavefield: step < 0");
     s->check_device();
     const size_t bytes = (size_t)s->n_shots * s->vec() * sizeof(double);
-    OVFEM_HIP(hipMemcpyAsync(s->u[s->cur].p, un, bytes, hipMemcpyDeviceToDevice, s->stream));
-    OVFEM_HIP(hipMemcpyAsync(s->u[s->cur ^ 1].p, unm1, bytes, hipMemcpyDeviceToDevice, s->stream));
-    s->launch_exponents(s->geom, s->u[s->cur].p, s->expo[s->cur].p, s->n_shots);
-    s->exp_valid = true;
+    OVFEM_HIP(hipMemcpyAsync(s->u[s->buf_cur(s->phase)].p, un, bytes, hipMemcpyDeviceToDevice, s->stream));
+    OVFEM_HIP(hipMemcpyAsync(s->u[s->buf_prev(s->phase)].p, unm1, bytes, hipMemcpyDeviceToDevice, s->stream));
+    s->state_exponents();
     s->step = step;
     s->ckpt_valid = false;
     OVFEM_HIP(hipStreamSynchronize(s->stream));
@@ -878,6 +962,57 @@ ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step) {
   return guarded([&] {
     require(s != nullptr && step != nullptr, "ovfem_get_step: NULL argument");
     *step = s->step;
+  });
+}
+
+ovfem_status ovfem_set_damping(ovfem_solver* s, double alpha, double beta) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_set_damping: solver is NULL");
+    require(std::isfinite(alpha) && std::isfinite(beta) && alpha >= 0.0 && beta >= 0.0,
+            "ovfem_set_damping: alpha and beta must be finite and >= 0");
+    s->check_device();
+    if (s->dt_set)
+      require(s->dt <= s->dt_limit(beta), "ovfem_set_damping: dt = " + std::to_string(s->dt) +
+                                              " exceeds the stability bound with this beta (" +
+                                              std::to_string(s->dt_limit(beta)) + ")");
+    if ((alpha != 0.0 || beta != 0.0) && !s->u[2].p) {
+      DevBuf<double> u2;
+      DevBuf<int> e2;
+      try {
+        u2.alloc((size_t)s->n_shots * s->vec());
+        e2.alloc((size_t)s->n_shots * s->geom.n_wg);
+      } catch (...) {
+        u2.free();
+        e2.free();
+        throw;
+      }
+      std::swap(s->u[2], u2);
+      std::swap(s->expo[2], e2);
+    }
+    OVFEM_HIP(hipStreamSynchronize(s->stream));
+    s->alpha = alpha;
+    s->beta = beta;
+    s->acoef_dirty = true;
+    s->invalidate_launches();
+    s->zero_state();
+    OVFEM_HIP(hipStreamSynchronize(s->stream));
+  });
+}
+
+ovfem_status ovfem_set_stages(ovfem_solver* s, int32_t stages) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_set_stages: solver is NULL");
+    require(stages >= 4 && stages <= 8, "ovfem_set_stages: stages must be in 4..8");
+    require(s->precision != OVFEM_INT8_BF16 || stages == 8,
+            "ovfem_set_stages: OVFEM_INT8_BF16 runs 8 digit stages only");
+    s->stages = stages;
+  });
+}
+
+ovfem_status ovfem_get_stages(ovfem_solver* s, int32_t* stages) {
+  return guarded([&] {
+    require(s != nullptr && stages != nullptr, "ovfem_get_stages: NULL argument");
+    *stages = s->stages;
   });
 }
 
@@ -931,8 +1066,9 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       // the state (wavefield pair, traces, step counter) is saved and restored
       keep.alloc(2 * nv);
       keep_tr.alloc(s->traces.n);
-      OVFEM_HIP(hipMemcpyAsync(keep.p, s->u[s->cur].p, bytes, hipMemcpyDeviceToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(keep.p + nv, s->u[s->cur ^ 1].p, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(keep.p, s->u[s->buf_cur(s->phase)].p, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(keep.p + nv, s->u[s->buf_prev(s->phase)].p, bytes, hipMemcpyDeviceToDevice,
+                               s->stream));
       OVFEM_HIP(hipMemcpyAsync(keep_tr.p, s->traces.p, s->traces.n * sizeof(double), hipMemcpyDeviceToDevice,
                                s->stream));
       OVFEM_HIP(hipEventCreate(&e0));
@@ -977,6 +1113,7 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       double best_graph = std::numeric_limits<double>::infinity();
       int best_gs = 0;
       for (int gs : {0, 64}) {
+        if (gs > 0 && s->damped()) continue;  // damped runs are not captured
         s->graph_steps = gs;
         s->invalidate_launches();
         s->do_steps(gs > 0 ? gs : 2);  // warm-up; captures the block
@@ -994,12 +1131,12 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       best = std::min(best, best_graph);
       s->graph_steps = best_gs;
       s->invalidate_launches();
-      OVFEM_HIP(hipMemcpyAsync(s->u[s->cur].p, keep.p, bytes, hipMemcpyDeviceToDevice, s->stream));
-      OVFEM_HIP(hipMemcpyAsync(s->u[s->cur ^ 1].p, keep.p + nv, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(s->u[s->buf_cur(s->phase)].p, keep.p, bytes, hipMemcpyDeviceToDevice, s->stream));
+      OVFEM_HIP(hipMemcpyAsync(s->u[s->buf_prev(s->phase)].p, keep.p + nv, bytes, hipMemcpyDeviceToDevice,
+                               s->stream));
       OVFEM_HIP(hipMemcpyAsync(s->traces.p, keep_tr.p, s->traces.n * sizeof(double), hipMemcpyDeviceToDevice,
                                s->stream));
-      s->launch_exponents(s->geom, s->u[s->cur].p, s->expo[s->cur].p, s->n_shots);
-      s->exp_valid = true;
+      s->state_exponents();
       s->step = step0;
       OVFEM_HIP(hipStreamSynchronize(s->stream));
     } catch (...) {
@@ -1046,6 +1183,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
             "then step from reset without changing precision, tiling or wavefield)",
             OVFEM_ESTATE);
     require(n >= 1, "ovfem_adjoint: no forward steps to differentiate", OVFEM_ESTATE);
+    require(!s->damped(), "ovfem_adjoint: the adjoint of the damped recursion is not provided", OVFEM_ESTATE);
     require(s->n_rec > 0 && n <= s->rec_nt, "ovfem_adjoint: receivers must record every forward step", OVFEM_ESTATE);
     require(s->model_set && s->dt_set, "ovfem_adjoint: model and dt not set", OVFEM_ESTATE);
     s->refresh_acoef();
@@ -1089,7 +1227,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       int wc = 0;  // w[wc] = w^{m+1}, w[wc ^ 1] = w^{m+2}; half wc of wexp: exponents of w[wc]
       s->launch_exponents(g, w[0], wexp.p, 1);
 
-      KArgs F = s->shot_args(0, s->cur);  // forward recompute: forward sources, no recording
+      KArgs F = s->shot_args(0, s->phase);  // forward recompute: forward sources, no recording
       F.rec_nt = 0;
       KArgs B = F;  // adjoint steps: the residual injected at the receivers
       B.src_ptr = d_aptr.p;
@@ -1116,7 +1254,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           F.unext = state(t - s0 + 1);
           F.exp_in = fexp.p + fe * g.n_wg;
           F.exp_out = fexp.p + (fe ^ 1) * g.n_wg;
-          launch_unit<MODE_STEP>(s->precision, F, nullptr, t, s->stream);
+          launch_unit<MODE_STEP>(s->form(), F, nullptr, t, s->stream);
           fe ^= 1;
         }
         for (int64_t m = e0; m > s0; --m) {
@@ -1125,7 +1263,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           B.unext = w[wc ^ 1];
           B.exp_in = wexp.p + wc * g.n_wg;
           B.exp_out = wexp.p + (wc ^ 1) * g.n_wg;
-          launch_unit<MODE_STEP>(s->precision, B, nullptr, m - 1, s->stream);
+          launch_unit<MODE_STEP>(s->form(), B, nullptr, m - 1, s->stream);
           wc ^= 1;
           ovfem_gradient_kernel<<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc], g_lam,
                                                                  g_mu);
@@ -1176,37 +1314,44 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
   return guarded([&] {
     require(b != nullptr, "ovfem_batch_step: batch is NULL");
     require(n >= 0, "ovfem_batch_step: n < 0");
-    const int precision = b->members[0]->precision;
+    const Form form = b->members[0]->form();
     double items = 0;
     for (auto* m : b->members) {
-      require(m->precision == precision, "ovfem_batch_step: members differ in precision", OVFEM_ESTATE);
+      require(m->form_code() == b->members[0]->form_code(), "ovfem_batch_step: members differ in precision or stages",
+              OVFEM_ESTATE);
+      require(m->damped() == form.damp, "ovfem_batch_step: damped and undamped members cannot share a batch",
+              OVFEM_ESTATE);
       m->check_device();
       items += (double)m->n_shots * m->geom.n_wg;
     }
     require(items < 2147483647.0, "ovfem_batch_step: too many work items");
     if (n == 0) return;
     for (auto* m : b->members) m->prepare_steps();
-    // one unit per shot of each member; table q holds the arguments for the steps of
-    // relative parity q (a member's buffer parity flips with every step)
+    // one unit per shot of each member; table q holds the arguments for relative steps
+    // i with i % 6 == q (a member's phase cycles with period 2, or 3 when damped)
+    constexpr int NQ = 6;
     std::vector<KArgs> t;
     std::vector<int> begin(1, 0);
-    for (int q = 0; q < 2; ++q)
-      for (auto* m : b->members)
+    for (int q = 0; q < NQ; ++q)
+      for (auto* m : b->members) {
+        int ph = m->phase;
+        for (int i = 0; i < q; ++i) ph = m->buf_next(ph);
         for (int s = 0; s < m->n_shots; ++s) {
-          KArgs A = m->shot_args(s, m->cur ^ q);
+          KArgs A = m->shot_args(s, ph);
           A.step = m->step;
           t.push_back(A);
           if (q == 0) begin.push_back(begin.back() + m->geom.n_wg);
         }
+      }
     const int n_units = (int)begin.size() - 1, total = begin.back();
     OVFEM_HIP(hipStreamSynchronize(b->stream));  // earlier batch launches may read the old tables
     upload(b->units, t, b->stream);
     upload(b->begin, begin, b->stream);
     for (int64_t i = 0; i < n; ++i)
-      launch_units(precision, b->units.p + (size_t)(i & 1) * n_units, b->begin.p, n_units, total, b->persist_groups,
+      launch_units(form, b->units.p + (size_t)(i % NQ) * n_units, b->begin.p, n_units, total, b->persist_groups,
                    nullptr, i, b->stream);
     for (auto* m : b->members) {
-      m->cur ^= (int)(n & 1);
+      for (int64_t i = 0; i < n % NQ; ++i) m->phase = m->buf_next(m->phase);
       m->step += n;
       m->ckpt_valid = false;
     }

@@ -41,6 +41,9 @@ SIGNATURES = {
     "ovfem_get_step": (_i32, [_vp, ctypes.POINTER(_i64)]),
     "ovfem_set_checkpointing": (_i32, [_vp, _i64, _i64]),
     "ovfem_adjoint": (_i32, [_vp, _vp, _vp, _vp]),
+    "ovfem_set_damping": (_i32, [_vp, _f64, _f64]),
+    "ovfem_set_stages": (_i32, [_vp, _i32]),
+    "ovfem_get_stages": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "ovfem_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
     "ovfem_get_tuning": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "ovfem_autotune": (_i32, [_vp, _i32, ctypes.POINTER(_f64)]),
@@ -242,6 +245,19 @@ class Solver:
     def get_step(self):
         v = ctypes.c_int64()
         _check(_LIB.ovfem_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    # --- Rayleigh damping C = alpha M + beta K
+    def set_damping(self, alpha, beta):
+        _check(_LIB.ovfem_set_damping(self._h, float(alpha), float(beta)))
+
+    # --- digit stages of the INT8 form
+    def set_stages(self, stages):
+        _check(_LIB.ovfem_set_stages(self._h, int(stages)))
+
+    def get_stages(self):
+        v = _i32()
+        _check(_LIB.ovfem_get_stages(self._h, ctypes.byref(v)))
         return v.value
 
     # --- launch configuration

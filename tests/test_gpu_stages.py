@@ -1,0 +1,147 @@
+"""GPU: the digit stage count M of the INT8 form (Sec. 2, Eqs. (16)-(17); Sec. 3, Table 3).
+
+The paper compares INT8 results with M = 4..8 stages against FP128/FP64/FP32: accuracy
+grows with M, M = 4 is about FP32 and M = 8 at least FP64.  Here q carries 8M - 2 bits
+under the tile exponent, and the same ordering is checked against the exact K u.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from paper_2404_13683_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+STAGES = [4, 5, 6, 7, 8]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _medium(nx, ny, nz, seed, h=2.0, nt=60):
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    rho = rng.uniform(1800, 2600, shape)
+    vs = rng.uniform(400, 2000, shape)
+    lam, mu = wl.lame_from_velocities(2.0 * vs, vs, rho)
+    dt = wl.stable_dt(h, lam, mu, rho)
+    src = np.array([wl.node_id(nx // 2, ny // 2, nz, nx, ny)], np.int64)
+    return wl.Workload("stages-medium", nx, ny, nz, h, lam, mu, rho, wl.box_fixed(nx, ny, nz), dt, nt,
+                       src, np.array([2], np.int32), np.array([0], np.int32),
+                       wl.ricker(nt, dt, 1.0 / (25 * dt))[None, :],
+                       wl.surface_nodes(rng, 6, nx, ny, nz, exclude=src))
+
+
+def _matvec(w, prec, u, stages=8):
+    import torch
+
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver.from_workload(w, precision=prec)
+    if prec == "int8":
+        s.set_stages(stages)
+    out = s.matvec(torch.from_numpy(np.ascontiguousarray(u).reshape(-1)).cuda()).cpu().numpy().reshape(u.shape)
+    s.close()
+    return out
+
+
+def _fp32_matvec_at(u, lam, mu, h, pts):
+    """K u at the listed nodes with every element product rounded in float32 (the
+    paper's FP32 comparison row)."""
+    from oracle import element as el
+    Kl, Km = (np.asarray(m, np.float32) for m in el.ovfem_reference())
+    out = np.zeros((len(pts), 3), np.float32)
+    nz, ny, nx = lam.shape
+    for r, (k, j, i) in enumerate(pts):
+        for alpha in range(8):
+            di, dj, dk = alpha & 1, (alpha >> 1) & 1, (alpha >> 2) & 1
+            ei, ej, ek = i - di, j - dj, k - dk
+            ue = np.concatenate([u[ek + ((b >> 2) & 1), ej + ((b >> 1) & 1), ei + (b & 1)]
+                                 for b in range(8)]).astype(np.float32)
+            ye = np.float32(h) * (np.float32(lam[ek, ej, ei]) * (Kl @ ue) + np.float32(mu[ek, ej, ei]) * (Km @ ue))
+            out[r] += ye[3 * alpha:3 * alpha + 3]
+    return out.astype(np.float64)
+
+
+def test_accuracy_grows_with_stages_as_in_table_3():
+    from oracle import element as el
+    nx, ny, nz = 20, 18, 17
+    w = _medium(nx, ny, nz, seed=19)
+    u = wl.random_field((nz + 1, ny + 1, nx + 1, 3), seed=23)
+    got = {M: _matvec(w, "int8", u, M) for M in STAGES}
+    got["fp64"] = _matvec(w, "fp64", u)
+    Kl, Km = el.ovfem_reference_exact()
+    rng = np.random.default_rng(4)
+    pts = [(int(rng.integers(1, nz)), int(rng.integers(1, ny)), int(rng.integers(1, nx))) for _ in range(30)]
+    fp32 = _fp32_matvec_at(u, w.lam, w.mu, w.h, pts)
+    errs = {key: [] for key in list(got) + ["fp32"]}
+    for r, (k, j, i) in enumerate(pts):
+        exact = [Fraction(0)] * 3
+        for alpha in range(8):
+            di, dj, dk = alpha & 1, (alpha >> 1) & 1, (alpha >> 2) & 1
+            ei, ej, ek = i - di, j - dj, k - dk
+            ue = [Fraction(float(u[ek + ((b >> 2) & 1), ej + ((b >> 1) & 1), ei + (b & 1), c]))
+                  for b in range(8) for c in range(3)]
+            L = Fraction(float(w.lam[ek, ej, ei])) * Fraction(w.h)
+            Mu = Fraction(float(w.mu[ek, ej, ei])) * Fraction(w.h)
+            for c in range(3):
+                row = 3 * alpha + c
+                exact[c] += (L * sum(Kl[row][q] * ue[q] for q in range(24))
+                             + Mu * sum(Km[row][q] * ue[q] for q in range(24)))
+        for c in range(3):
+            ex = float(exact[c])
+            for key in got:
+                errs[key].append(abs(float(Fraction(float(got[key][k, j, i, c])) - exact[c])) / abs(ex))
+            errs["fp32"].append(abs(fp32[r, c] - ex) / abs(ex))
+    med = {key: float(np.median(v)) for key, v in errs.items()}
+    print("median rel error vs exact K u:", {k: "%.2e" % v for k, v in med.items()})
+    # each stage adds 8 bits until the FP64 rounding of the recombination is reached
+    for M in (5, 6, 7):
+        assert med[M] < med[M - 1] / 16
+    assert med[8] <= med["fp64"]
+    # M = 4 (30 bits) is of FP32's order: not worse than a float32 evaluation
+    assert med[4] <= med["fp32"] and med[4] > 1e-12
+    # the full default is bitwise the M = 8 form
+    assert np.array_equal(got[8], _matvec(w, "int8", u))
+
+
+def test_traces_per_stage_count():
+    """C1 recipe (16^3, 200 steps): trace error against the oracle for every M."""
+    from paper_2404_13683_amd.ovfem import Solver
+    w = wl.homogeneous_c1()
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    ref, _, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    err = {}
+    for M in STAGES:
+        s = Solver.from_workload(w, precision="int8")
+        s.set_stages(M)
+        s.step(w.nt)
+        err[M] = _rel(s.get_traces().cpu().numpy()[0], ref)
+        s.close()
+    print("C1 trace rel L2 per stage count:", {k: "%.2e" % v for k, v in err.items()})
+    assert err[8] <= 1e-9 and err[7] <= 1e-9
+    for M in (5, 6, 7):
+        assert err[M] <= err[M - 1]
+    assert err[4] < 1e-3
+
+
+def test_stage_count_validation():
+    from paper_2404_13683_amd.ovfem import Batch, OvfemError, Solver
+    w = wl.homogeneous_c1(nx=6, ny=6, nz=6, nt=10)
+    s = Solver.from_workload(w, precision="int8")
+    for bad in (3, 9, 0):
+        with pytest.raises(OvfemError):
+            s.set_stages(bad)
+    s.set_stages(6)
+    assert s.get_stages() == 6
+    with pytest.raises(OvfemError):
+        s.set_precision("int8-bf16")  # the bf16 form runs 8 stages only
+    t = Solver.from_workload(w, precision="int8")
+    b = Batch([s, t])
+    with pytest.raises(OvfemError):
+        b.step(1)  # members differ in stage count
+    t.set_stages(6)
+    b.step(2)
+    b.close()
