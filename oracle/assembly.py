@@ -28,7 +28,7 @@ What is computed, all in float64:
 """
 import numpy as np
 
-from .element import ovfem_reference
+from .element import ovfem_reference, trilinear_reference
 
 
 def corner_slices(nx, ny, nz):
@@ -105,7 +105,7 @@ def rayleigh_coefficients(zeta, f1, f2):
 class Model:
     """Inputs of one simulation, plus the oracle's own derived mass."""
 
-    def __init__(self, lam, mu, rho, h, fixed, dt, solid=None, alpha=0.0, beta=0.0):
+    def __init__(self, lam, mu, rho, h, fixed, dt, solid=None, alpha=0.0, beta=0.0, element="ovfem"):
         self.lam = np.asarray(lam, dtype=np.float64)
         self.mu = np.asarray(mu, dtype=np.float64)
         self.rho = np.asarray(rho, dtype=np.float64)
@@ -124,9 +124,12 @@ class Model:
         self.a[self.free] = self.dt ** 2 / self.mass[self.free]
         self.alpha = float(alpha)
         self.beta = float(beta)
+        # element matrices: OVFEM (Eq. (5)) or the lumped trilinear element ("VFEM"),
+        # both with the same diagonal mass rho h^3 / 8 per node and element
+        self.Kref = ovfem_reference() if element == "ovfem" else trilinear_reference()
 
     def K(self, u):
-        return matvec(u, self.lam, self.mu, self.h)
+        return matvec(u, self.lam, self.mu, self.h, self.Kref)
 
     def step(self, u, u_prev, F):
         """One central-difference step; returns u^{n+1}."""

@@ -31,7 +31,8 @@ Trilinear element (the conventional voxel element of Sec. 2, "VFEM").  The print
 basis carries a sign/shift typo; the standard trilinear basis
 (1/8) prod (1 + rbar_i r_i) is used, integrated with 2x2x2 Gauss points (the
 "8-point integration" mentioned in Sec. 3), with the lumped mass rho h^3 / 8 per
-node.  It is used only by the dispersion comparison tests.
+node.  It serves the dispersion comparison and, as the comparison element of Sec. 3,
+the element option of the stepper.
 """
 from fractions import Fraction
 import itertools
@@ -237,3 +238,10 @@ def trilinear_stiffness(lam, mu, h=1.0):
                     B[v, 3 * alpha + q] += dN[p, alpha]
         K += B.T @ C @ B * (h / 2.0) ** 3  # unit Gauss weights
     return K
+
+
+def trilinear_reference():
+    """(K_lam, K_mu) of the trilinear element for h = 1 (float64): K_e = h (lam K_lam + mu K_mu)."""
+    if "trilinear" not in _CACHE:
+        _CACHE["trilinear"] = (trilinear_stiffness(1.0, 0.0, 1.0), trilinear_stiffness(0.0, 1.0, 1.0))
+    return _CACHE["trilinear"]

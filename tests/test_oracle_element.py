@@ -155,3 +155,65 @@ def test_trilinear_element_sanity():
     assert np.linalg.matrix_rank(K, tol=1e-10 * ev.max()) == 18
     for v in _rigid_modes():
         assert np.abs(K @ np.array([float(x) for x in v])).max() < 1e-12
+
+
+def _trilinear_closed_form():
+    """Trilinear K_lam, K_mu (h = 1) from exact polynomial integrals, in rationals.
+
+    With N_a = (1/8) prod_k (1 + s_ak r_k) on [-1, 1]^3 (x = (r + 1)/2):
+      int dN_a/dr_i dN_b/dr_i = (1/64) s_ai s_bi * 2 * prod_{k != i} (2 + (2/3) s_ak s_bk),
+      int dN_a/dr_i dN_b/dr_j = (1/64) s_ai s_bj * 2 * 2 * (2 + (2/3) s_al s_bl),  i != j, l the third axis,
+    and d/dx = 2 d/dr, dx = dr / 8, so G_ij(a, b) = int dN_a/dx_i dN_b/dx_j dx = (1/2) * (r-integral).
+    K_lam[3a+c][3b+d] = G_cd(a, b); K_mu[3a+c][3b+d] = delta_cd sum_k G_kk(a, b) + G_dc(a, b).
+    """
+    from fractions import Fraction as Fr
+    s = [el.node_rbar(a) for a in range(8)]
+    G = {}
+    for a in range(8):
+        for b in range(8):
+            for i in range(3):
+                for j in range(3):
+                    if i == j:
+                        v = Fr(2)
+                        for k in range(3):
+                            if k != i:
+                                v *= 2 + Fr(2, 3) * s[a][k] * s[b][k]
+                    else:
+                        l = 3 - i - j
+                        v = 4 * (2 + Fr(2, 3) * s[a][l] * s[b][l])
+                    G[a, b, i, j] = Fr(1, 2) * Fr(1, 64) * s[a][i] * s[b][j] * v
+    Kl = [[G[m // 3, n // 3, m % 3, n % 3] for n in range(24)] for m in range(24)]
+    Km = [[(sum(G[m // 3, n // 3, k, k] for k in range(3)) if m % 3 == n % 3 else 0) + G[m // 3, n // 3, n % 3, m % 3]
+           for n in range(24)] for m in range(24)]
+    return Kl, Km
+
+
+def test_trilinear_reference_equals_its_closed_form_and_is_72_integral():
+    """The 2x2x2 Gauss integration is exact for the trilinear stiffness (polynomial of
+    degree 2 per axis): the oracle's matrices equal the closed-form integrals, and
+    72 K_lam, 72 K_mu are integer matrices (the INT8 scaling of this element)."""
+    Kl, Km = el.trilinear_reference()
+    Cl, Cm = _trilinear_closed_form()
+    for K, C in ((Kl, Cl), (Km, Cm)):
+        C = np.array([[float(x) for x in r] for r in C])
+        assert np.abs(K - C).max() < 1e-15
+        assert np.abs(72 * K - np.round(72 * K)).max() < 1e-12
+    Cl, Cm = _trilinear_closed_form()
+    assert all((72 * x).denominator == 1 for r in Cl + Cm for x in r)
+    assert max(abs(72 * x) for r in Cl for x in r) == 8     # 72 K_lam in [-8, 8]
+    assert max(abs(72 * x) for r in Cm for x in r) == 32    # diagonal of 72 K_mu
+    # the known diagonal of the unit brick: K_lam[0][0] = 1/9, K_mu[0][0] = 4/9
+    assert Cl[0][0] == Fraction(1, 9) and Cm[0][0] == Fraction(4, 9)
+
+
+def test_trilinear_constant_strain_energy():
+    """Patch test of the element: a linear field's strain energy equals the continuum's."""
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((3, 3))
+    E = 0.5 * (E + E.T)
+    h, lam, mu = 0.7, 2.3, 1.1
+    Kl, Km = el.trilinear_reference()
+    u = np.concatenate([h * (np.array(el.node_rbar(a)) + 1) / 2 @ E for a in range(8)])
+    energy = 0.5 * u @ (h * (lam * Kl + mu * Km)) @ u
+    cont = 0.5 * h ** 3 * (lam * np.trace(E) ** 2 + 2 * mu * np.sum(E * E))
+    assert abs(energy - cont) <= 1e-13 * cont
