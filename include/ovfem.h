@@ -55,6 +55,10 @@ typedef int32_t ovfem_status;
 #define OVFEM_EDEVICE (-3) /* HIP runtime or kernel launch error */
 #define OVFEM_ESTATE (-4)  /* call not valid in the solver's current state */
 
+/* element type (ovfem_set_element) */
+#define OVFEM_ELEMENT_OVFEM 0     /* the orthogonal voxel element of Sec. 2 (default) */
+#define OVFEM_ELEMENT_TRILINEAR 1 /* the conventional lumped trilinear voxel element ("VFEM") */
+
 /* precision of the element products */
 #define OVFEM_FP64 0
 #define OVFEM_INT8 1      /* INT8 digit slices, int8 matrix cores, INT32 accumulation */
@@ -178,6 +182,15 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
  * precision for K.  The wavefield state and traces of the forward run are unchanged.
  * Synchronises the stream.  ESTATE if the preconditions do not hold. */
 ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_lam, double* g_mu);
+
+/* Element type: OVFEM_ELEMENT_OVFEM (default) or OVFEM_ELEMENT_TRILINEAR, the
+ * conventional voxel element the paper compares against (Sec. 2: trilinear basis,
+ * integrated exactly by 2x2x2 Gauss points; the same lumped mass rho h^3 / 8 per node
+ * and element).  Its matrices scaled by 72 are integer matrices in -32..32, so every
+ * precision runs it (FP64 with the matrices as constants, the INT8 forms with them as
+ * A operands, material scaled by h lam / 72, h mu / 72).  Clears the model and dt (set
+ * them again) and resets the wavefield.  EINVAL for an unknown element. */
+ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element);
 
 /* Rayleigh damping C = alpha M + beta K (alpha, beta >= 0; both 0 = undamped, the
  * default).  The paper's experiment (Sec. 3) uses Rayleigh damping without printing its

@@ -178,9 +178,9 @@ def energy(model, u_next, u):
     return kin + pot
 
 
-def element_forms(ue, we, h):
+def element_forms(ue, we, h, K=None):
     """Per element: h w_e^T K_lam u_e and h w_e^T K_mu u_e (the d(w^T K u)/d lam_e, mu_e)."""
-    Kl, Km = ovfem_reference()
+    Kl, Km = ovfem_reference() if K is None else K
     return (h * np.einsum("...i,...i->...", we, ue @ Kl.T),
             h * np.einsum("...i,...i->...", we, ue @ Km.T))
 
@@ -246,7 +246,7 @@ def adjoint_gradient(model, nt, src_node, src_comp, wavelet, rec_node, d_obs, ck
             wm = 2.0 * w1 - w2 - A * model.K(w1) + A * src
             wm[~model.free] = 0.0
             gl, gm = element_forms(gather(states[m - 1 - s], nx, ny, nz),
-                                   gather(wm, nx, ny, nz), model.h)
+                                   gather(wm, nx, ny, nz), model.h, model.Kref)
             g_lam -= gl
             g_mu -= gm
             w2, w1 = w1, wm

@@ -267,14 +267,15 @@ __device__ inline void stage_digits_i8(const D3& u, int E, uint32_t* dst) {
 }
 
 // Per-element FP64 product: y = lam_s AL ue + mu_s AM ue.
+template <int ELEM>
 __device__ inline void element_fp64(const double ue[24], double lam_s, double mu_s, double y[24]) {
 #pragma unroll
   for (int m = 0; m < 24; ++m) {
     double sl = 0.0, sm = 0.0;
 #pragma unroll
     for (int n = 0; n < 24; ++n) {
-      sl = fma((double)kRef.AL[m][n], ue[n], sl);
-      sm = fma((double)kRef.AM[m][n], ue[n], sm);
+      sl = fma((double)elem_al<ELEM>(m, n), ue[n], sl);
+      sm = fma((double)elem_am<ELEM>(m, n), ue[n], sm);
     }
     y[m] = lam_s * sl + mu_s * sm;
   }
@@ -318,7 +319,12 @@ __device__ inline void write_tile_exponent(double local_max, int* dst, double* r
 // One work-group tile (tile index wg of its unit) of one time step (or one matvec).
 // M: digit stages of PATH_INT8 (the other paths take M = 8).  DAMP: Rayleigh-damped
 // step (MODE_STEP only).
-template <int PATH, int MODE, int M, bool DAMP = false>
+// LATE: load the owned node's u^n, u^{n-1} and dt^2/m just before its update instead of
+// carrying them through the element phase (fewer live registers: the INT8 one-unit
+// kernel then fits 128 VGPRs, four waves per SIMD).
+// ELEM: element matrices of the FP64 path (0 OVFEM, 1 trilinear); the INT8 paths take
+// theirs from the A-operand tables.
+template <int PATH, int MODE, int M, bool DAMP = false, bool LATE = false, int ELEM = 0>
 __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const long long step) {
   static_assert(!DAMP || MODE == MODE_STEP, "damping applies to time steps");
   using St = Stages<M>;
@@ -462,20 +468,24 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     const bool do_node = it >= 1 && owner_in;
     const size_t node_off = (size_t)k * plane_bytes + main_ref.off;  // byte offset of owned node
     double up[3] = {0.0, 0.0, 0.0}, ac = 0.0;
-    if (do_node && MODE == MODE_STEP) {
-      const double* pp = reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.uprev) + node_off);
-      up[0] = pp[0];
-      up[1] = pp[1];
-      up[2] = pp[2];
-      if constexpr (DAMP) {
-        const double* pu = reinterpret_cast<const double*>(u_base + node_off);
-        u_own_bot.v[0] = pu[0];
-        u_own_bot.v[1] = pu[1];
-        u_own_bot.v[2] = pu[2];
+    auto load_node_state = [&]() {
+      if (do_node && MODE == MODE_STEP) {
+        const double* pp =
+            reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.uprev) + node_off);
+        up[0] = pp[0];
+        up[1] = pp[1];
+        up[2] = pp[2];
+        if constexpr (DAMP || LATE) {
+          const double* pu = reinterpret_cast<const double*>(u_base + node_off);
+          u_own_bot.v[0] = pu[0];
+          u_own_bot.v[1] = pu[1];
+          u_own_bot.v[2] = pu[2];
+        }
+        ac = *reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.acoef) +
+                                              (size_t)k * (plane_bytes / 3) + main_ref.off / 3);
       }
-      ac = *reinterpret_cast<const double*>(reinterpret_cast<const unsigned char*>(A.acoef) +
-                                            (size_t)k * (plane_bytes / 3) + main_ref.off / 3);
-    }
+    };
+    if constexpr (!LATE) load_node_state();
     const bool layer_ok = k >= 0 && k < g.nz;
     __syncthreads();
 
@@ -493,7 +503,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 #pragma unroll
           for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PN + tb + dj) * PN + ta + di];
         }
-        element_fp64(ue, mat_e.x, mat_e.y, y);
+        element_fp64<ELEM>(ue, mat_e.x, mat_e.y, y);
       } else {
 #pragma unroll
         for (int i = 0; i < 24; ++i) y[i] = 0.0;
@@ -616,6 +626,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     __syncthreads();
 
     // ---- node phase for plane Z = k (owned when it >= 1)
+    if constexpr (LATE) load_node_state();
     if (do_node) {
       const int p = ta + 1, q = tb + 1;
       double f[3];
@@ -675,11 +686,11 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 // One unit (one shot of one grid): one work-group per tile.  The step index is
 // *step_base + step (step_base may be null), so a captured sequence of launches can
 // be replayed with a step base kept in device memory.
-template <int PATH, int MODE, int M = 8, bool DAMP = false>
+template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
 __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
     ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
-  layer_tile<PATH, MODE, M, DAMP>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
+  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
 }
 
 // Many units in one launch (the shots of a grid, or grids of uneven size): unit u owns
@@ -687,7 +698,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
 // gets a contiguous run; a grid smaller than the work list strides over it (the grid
 // size is then a multiple of 8, so a work-group stays on one XCD's run).  The unit's
 // own step offset is units[u].step.
-template <int PATH, int MODE, int M = 8, bool DAMP = false>
+template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
 __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
     ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                        const long long* step_base, long long step) {
@@ -701,7 +712,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
       else hi = mid - 1;
     }
     const KArgs A = units[lo];
-    layer_tile<PATH, MODE, M, DAMP>(A, item - unit_begin[lo], s + A.step);
+    layer_tile<PATH, MODE, M, DAMP, false, ELEM>(A, item - unit_begin[lo], s + A.step);
     __syncthreads();  // LDS is reused by the next work item
   }
 }
@@ -741,7 +752,8 @@ __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const doub
 //     g_lam[e] -= h w_e^T K_lam u_e,   g_mu[e] -= h w_e^T K_mu u_e,
 // with u = u^{m-1} and w = w^m (the derivative of w^T K u with respect to lam_e, mu_e,
 // from K_e = h (lam_e K_lam + mu_e K_mu)).  One thread per element; each element's
-// sums are private, so the accumulation order is fixed.
+// sums are private, so the accumulation order is fixed.  ELEM: 0 OVFEM, 1 trilinear.
+template <int ELEM>
 __global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, const double* mat,
                                                                const double* u, const double* w,
                                                                double* g_lam, double* g_mu) {
@@ -768,14 +780,14 @@ __global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, 
     double sl = 0.0, sm = 0.0;
 #pragma unroll
     for (int q = 0; q < 24; ++q) {
-      sl = fma((double)kRef.AL[r][q], ue[q], sl);
-      sm = fma((double)kRef.AM[r][q], ue[q], sm);
+      sl = fma((double)elem_al<ELEM>(r, q), ue[q], sl);
+      sm = fma((double)elem_am<ELEM>(r, q), ue[q], sm);
     }
     gl = fma(we[r], sl, gl);
     gm = fma(we[r], sm, gm);
   }
-  g_lam[e] -= h / 256.0 * gl;
-  g_mu[e] -= h / 128.0 * gm;
+  g_lam[e] -= h / kElemScaleLam[ELEM] * gl;
+  g_mu[e] -= h / kElemScaleMu[ELEM] * gm;
 }
 
 }  // namespace ovfem

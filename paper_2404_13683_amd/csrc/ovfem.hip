@@ -116,24 +116,26 @@ double max_eigenvalue(std::vector<double> a, int n) {
 // of the 16 x 32 tile.  Row i of tile t is output s = 4 t + i % 4 for in-plane corner
 // G = i / 4: s < 6 are rows of AL, s >= 6 rows of AM, at corner G + 4 ((s % 6) / 3)
 // and component s % 3.  Column k is (node k / 4, component k % 4), component 3 padding.
-int alane_entry(int t, int l, int q) {
+int alane_entry(int elem, int t, int l, int q) {
   const int i = l % 16, kg = l / 16;
   const int G = i / 4, s = 4 * t + i % 4;
   const int which = s / 6, dk = (s % 6) / 3, c = s % 3;
   const int m = 3 * (G + 4 * dk) + c;
   const int k = 8 * kg + q, node = k / 4, cp = k % 4;
   if (cp == 3) return 0;
-  return which == 0 ? kRef.AL[m][3 * node + cp] : kRef.AM[m][3 * node + cp];
+  const int n = 3 * node + cp;
+  if (elem == OVFEM_ELEMENT_TRILINEAR) return which == 0 ? kTri.AL[m][n] : kTri.AM[m][n];
+  return which == 0 ? kRef.AL[m][n] : kRef.AM[m][n];
 }
 
 // bf16 form, two entries per 32-bit word: |entry| <= 127 has at most 7 significant
 // bits, so the upper half of its FP32 encoding is exact.
-std::vector<uint32_t> make_alane_bf16() {
+std::vector<uint32_t> make_alane_bf16(int elem) {
   std::vector<uint32_t> out(3 * 64 * 4, 0);
   for (int t = 0; t < 3; ++t)
     for (int l = 0; l < 64; ++l)
       for (int q = 0; q < 8; ++q) {
-        const float f = (float)alane_entry(t, l, q);
+        const float f = (float)alane_entry(elem, t, l, q);
         uint32_t bits;
         std::memcpy(&bits, &f, 4);
         out[(t * 64 + l) * 4 + q / 2] |= (bits >> 16) << (16 * (q % 2));
@@ -142,12 +144,12 @@ std::vector<uint32_t> make_alane_bf16() {
 }
 
 // int8 form, eight entries per 64-bit word.
-std::vector<uint64_t> make_alane_i8() {
+std::vector<uint64_t> make_alane_i8(int elem) {
   std::vector<uint64_t> out(3 * 64, 0);
   for (int t = 0; t < 3; ++t)
     for (int l = 0; l < 64; ++l)
       for (int q = 0; q < 8; ++q)
-        out[t * 64 + l] |= (uint64_t)(uint8_t)(int8_t)alane_entry(t, l, q) << (8 * q);
+        out[t * 64 + l] |= (uint64_t)(uint8_t)(int8_t)alane_entry(elem, t, l, q) << (8 * q);
   return out;
 }
 
@@ -158,6 +160,7 @@ struct Form {
   int precision;
   int stages;
   bool damp;  // Rayleigh-damped step kernels
+  int elem;   // OVFEM_ELEMENT_*: selects the FP64 path's compile-time element matrices
 };
 
 // One unit, one work-group per tile.
@@ -165,7 +168,10 @@ template <int MODE, bool D>
 void launch_unit_form(Form f, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
   const dim3 grid(A.g.n_wg), block(NTHR);
   if (f.precision == OVFEM_FP64) {
-    ovfem_layer_kernel<PATH_FP64, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
+    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
+      ovfem_layer_kernel<PATH_FP64, MODE, 8, D, 1><<<grid, block, 0, stream>>>(A, base, step);
+    else
+      ovfem_layer_kernel<PATH_FP64, MODE, 8, D, 0><<<grid, block, 0, stream>>>(A, base, step);
   } else if (f.precision == OVFEM_INT8) {
     switch (f.stages) {
       case 4: ovfem_layer_kernel<PATH_INT8, MODE, 4, D><<<grid, block, 0, stream>>>(A, base, step); break;
@@ -199,7 +205,10 @@ void launch_units_form(Form f, dim3 g, const KArgs* units, const int* begin, int
   const dim3 block(NTHR);
   const auto U = units;
   if (f.precision == OVFEM_FP64) {
-    ovfem_batch_kernel<PATH_FP64, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
+    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
+      ovfem_batch_kernel<PATH_FP64, MODE_STEP, 8, D, 1><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
+    else
+      ovfem_batch_kernel<PATH_FP64, MODE_STEP, 8, D, 0><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
   } else if (f.precision == OVFEM_INT8) {
     switch (f.stages) {
       case 4: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 4, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
@@ -264,6 +273,7 @@ struct ovfem_solver {
   int n_shots = 1;
   int precision = OVFEM_FP64;
   int stages = 8;  // digit stages M of OVFEM_INT8
+  int element = OVFEM_ELEMENT_OVFEM;
   Geom geom{};
   size_t n_nodes = 0, n_elem = 0;
 
@@ -332,8 +342,8 @@ struct ovfem_solver {
   int buf_cur(int ph) const { return ph; }
   int buf_prev(int ph) const { return damped() ? (ph + 2) % 3 : ph ^ 1; }
   int buf_next(int ph) const { return damped() ? (ph + 1) % 3 : ph ^ 1; }
-  Form form() const { return Form{precision, stages, damped()}; }
-  int form_code() const { return precision * 16 + (precision == OVFEM_INT8 ? stages : 0); }
+  Form form() const { return Form{precision, stages, damped(), element}; }
+  int form_code() const { return element * 256 + precision * 16 + (precision == OVFEM_INT8 ? stages : 0); }
   double damp_b() const { return beta / dt; }
   double damp_a() const { return 0.5 * alpha * dt; }
   // stability of the (damped) recursion for the largest mode: w^2 dt (dt + 2 beta) <= 4
@@ -688,8 +698,8 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
       s->expo[1].alloc((size_t)n_shots * g.n_wg);
       s->expo_tmp.alloc(g.n_wg);
       s->step_base.alloc(1);
-      upload(s->alane_bf16, make_alane_bf16(), s->stream);
-      upload(s->alane_i8, make_alane_i8(), s->stream);
+      upload(s->alane_bf16, make_alane_bf16(OVFEM_ELEMENT_OVFEM), s->stream);
+      upload(s->alane_i8, make_alane_i8(OVFEM_ELEMENT_OVFEM), s->stream);
       s->wavelet.alloc(1);
       s->traces.alloc(1);
       s->src = s->build_sources(g, {}, {}, {});
@@ -731,11 +741,13 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
     const double h = s->h;
     std::vector<double> mt(2 * ne), mass(s->n_nodes, 0.0);
     // stability: largest eigenvalues of the two reference matrices
+    const bool tri = s->element == OVFEM_ELEMENT_TRILINEAR;
+    const double sl = kElemScaleLam[tri ? 1 : 0], sm = kElemScaleMu[tri ? 1 : 0];
     std::vector<double> al(576), am(576);
     for (int i = 0; i < 24; ++i)
       for (int j = 0; j < 24; ++j) {
-        al[i * 24 + j] = kRef.AL[i][j] / 256.0;
-        am[i * 24 + j] = kRef.AM[i][j] / 128.0;
+        al[i * 24 + j] = (tri ? kTri.AL[i][j] : kRef.AL[i][j]) / sl;
+        am[i * 24 + j] = (tri ? kTri.AM[i][j] : kRef.AM[i][j]) / sm;
       }
     const double el = max_eigenvalue(al, 24), em = max_eigenvalue(am, 24);
     double wmax2 = 0.0;
@@ -753,8 +765,8 @@ ovfem_status ovfem_set_model(ovfem_solver* s, const double* lam, const double* m
                   "ovfem_set_model: non-finite material in element " + std::to_string(e));
           require(M > 0 && L + 2.0 * M / 3.0 > 0 && R > 0,
                   "ovfem_set_model: need mu > 0, lam + 2 mu / 3 > 0, rho > 0 (element " + std::to_string(e) + ")");
-          mt[2 * e] = h * L / 256.0;
-          mt[2 * e + 1] = h * M / 128.0;
+          mt[2 * e] = h * L / sl;
+          mt[2 * e + 1] = h * M / sm;
           const double me = R * h * h * h / 8.0;
           // lambda_max(lam K_lam + mu K_mu) <= max(lam, 0) lambda_max(K_lam) + mu lambda_max(K_mu)
           wmax2 = std::max(wmax2, h * (std::max(L, 0.0) * el + M * em) / me);
@@ -962,6 +974,36 @@ ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step) {
   return guarded([&] {
     require(s != nullptr && step != nullptr, "ovfem_get_step: NULL argument");
     *step = s->step;
+  });
+}
+
+ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_set_element: solver is NULL");
+    require(element == OVFEM_ELEMENT_OVFEM || element == OVFEM_ELEMENT_TRILINEAR, "ovfem_set_element: unknown element");
+    s->check_device();
+    if (element == s->element) return;
+    DevBuf<uint32_t> bf;
+    DevBuf<uint64_t> i8;
+    try {
+      upload(bf, make_alane_bf16(element), s->stream);
+      upload(i8, make_alane_i8(element), s->stream);
+      OVFEM_HIP(hipStreamSynchronize(s->stream));
+    } catch (...) {
+      bf.free();
+      i8.free();
+      throw;
+    }
+    std::swap(s->alane_bf16, bf);
+    std::swap(s->alane_i8, i8);
+    bf.free();
+    i8.free();
+    s->element = element;
+    s->model_set = false;  // the stored material scaling belongs to the element
+    s->dt_set = false;
+    s->invalidate_launches();
+    s->zero_state();
+    OVFEM_HIP(hipStreamSynchronize(s->stream));
   });
 }
 
@@ -1265,8 +1307,12 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           B.exp_out = wexp.p + (wc ^ 1) * g.n_wg;
           launch_unit<MODE_STEP>(s->form(), B, nullptr, m - 1, s->stream);
           wc ^= 1;
-          ovfem_gradient_kernel<<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc], g_lam,
-                                                                 g_mu);
+          if (s->element == OVFEM_ELEMENT_TRILINEAR)
+            ovfem_gradient_kernel<1><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc],
+                                                                      g_lam, g_mu);
+          else
+            ovfem_gradient_kernel<0><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc],
+                                                                      g_lam, g_mu);
           OVFEM_HIP(hipGetLastError());
         }
       }

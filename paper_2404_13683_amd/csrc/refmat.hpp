@@ -1,4 +1,5 @@
-// Integer reference matrices of the OVFEM voxel element, derived at compile time.
+// Integer reference matrices of the voxel elements, derived at compile time: the OVFEM
+// element (below) and the trilinear comparison element (further down).
 //
 // Sec. 2, Eq. (5): K_e = (psi grad phi)^T (psi psi)^{-1} c (psi grad phi), with the
 // octant-indicator displacement basis of Eq. (7) and the seven stress monomials of
@@ -126,6 +127,69 @@ constexpr RefMats make_refmats() {
 inline constexpr RefMats kRef = make_refmats();
 static_assert(kRef.ok, "OVFEM reference matrices must be integral INT8 after scaling by 256 / 128");
 
+// The conventional trilinear voxel element ("VFEM", the comparison element of Sec. 3):
+// N_a = (1/8) prod_k (1 + s_ak r_k) with the Galerkin stiffness integrated exactly (the
+// "8-point integration" is exact for it).  With G_ij(a, b) = int dN_a/dx_i dN_b/dx_j
+// over the unit voxel (d/dx = 2 d/dr, dx = dr / 8):
+//   G_ii(a, b) = (1/64) s_ai s_bi prod_{k != i} int (1 + s_ak r)(1 + s_bk r) dr,
+//   G_ij(a, b) = (1/64) s_ai s_bj * 4 * int (1 + s_al r)(1 + s_bl r) dr (l the third axis),
+// with int_{-1}^{1} (1 + s r)(1 + t r) dr = 2 + (2/3) s t; then
+//   K_lam[3a+c][3b+d] = G_cd(a, b),  K_mu[3a+c][3b+d] = delta_cd sum_k G_kk(a, b) + G_dc(a, b),
+// and AL = 72 K_lam, AM = 72 K_mu are integer matrices (checked below).
+constexpr Rat lin_pair_integral(int s, int t) { return radd(rat(2, 1), rat(2 * s * t, 3)); }
+
+constexpr Rat trilinear_g(int a, int b, int i, int j) {
+  Rat v = rat(corner_sign(a, i) * corner_sign(b, j), 64);
+  if (i == j) {
+    v = rmul(v, rat(2, 1));
+    for (int k = 0; k < 3; ++k)
+      if (k != i) v = rmul(v, lin_pair_integral(corner_sign(a, k), corner_sign(b, k)));
+  } else {
+    const int l = 3 - i - j;
+    v = rmul(v, rmul(rat(4, 1), lin_pair_integral(corner_sign(a, l), corner_sign(b, l))));
+  }
+  return rmul(v, rat(1, 2));  // r-space to x-space for h = 1: (2)^2 (1/2)^3
+}
+
+struct ElemMats {
+  int AL[24][24];
+  int AM[24][24];
+  int scale_lam, scale_mu;  // AL = scale_lam K_lam, AM = scale_mu K_mu
+  bool ok;
+};
+
+constexpr ElemMats make_trilinear() {
+  ElemMats R{};
+  R.ok = true;
+  R.scale_lam = 72;
+  R.scale_mu = 72;
+  for (int m = 0; m < 24; ++m)
+    for (int n = 0; n < 24; ++n) {
+      const int a = m / 3, c = m % 3, b = n / 3, d = n % 3;
+      Rat kl = trilinear_g(a, b, c, d);
+      Rat km = trilinear_g(a, b, d, c);
+      if (c == d)
+        for (int k = 0; k < 3; ++k) km = radd(km, trilinear_g(a, b, k, k));
+      const Rat al = rmul(kl, rat(72, 1)), am = rmul(km, rat(72, 1));
+      if (al.d != 1 || am.d != 1) R.ok = false;
+      if (al.n < -128 || al.n > 127 || am.n < -128 || am.n > 127) R.ok = false;
+      R.AL[m][n] = static_cast<int>(al.n);
+      R.AM[m][n] = static_cast<int>(am.n);
+    }
+  return R;
+}
+
+inline constexpr ElemMats kTri = make_trilinear();
+static_assert(kTri.ok, "trilinear reference matrices must be integral INT8 after scaling by 72");
+
+// The element types: 0 = OVFEM, 1 = trilinear.
+constexpr int kElemScaleLam[2] = {256, 72};
+constexpr int kElemScaleMu[2] = {128, 72};
+template <int ELEM>
+constexpr int elem_al(int m, int n) { return ELEM == 0 ? kRef.AL[m][n] : kTri.AL[m][n]; }
+template <int ELEM>
+constexpr int elem_am(int m, int n) { return ELEM == 0 ? kRef.AM[m][n] : kTri.AM[m][n]; }
+
 // Largest row sum of |AL| and |AM|: bounds a single INT8 product stage.
 constexpr int max_row_abs(const int (&A)[24][24]) {
   int best = 0;
@@ -136,7 +200,11 @@ constexpr int max_row_abs(const int (&A)[24][24]) {
   }
   return best;
 }
-inline constexpr int kMaxRowAbs = max_row_abs(kRef.AL) > max_row_abs(kRef.AM) ? max_row_abs(kRef.AL)
-                                                                             : max_row_abs(kRef.AM);
+constexpr int max4(int a, int b, int c, int d) {
+  const int x = a > b ? a : b, y = c > d ? c : d;
+  return x > y ? x : y;
+}
+inline constexpr int kMaxRowAbs =
+    max4(max_row_abs(kRef.AL), max_row_abs(kRef.AM), max_row_abs(kTri.AL), max_row_abs(kTri.AM));
 
 }  // namespace ovfem

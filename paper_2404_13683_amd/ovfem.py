@@ -18,6 +18,7 @@ OVFEM_FP64 = 0
 OVFEM_INT8 = 1
 OVFEM_INT8_BF16 = 2
 PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8, "int8-bf16": OVFEM_INT8_BF16}
+ELEMENTS = {"ovfem": 0, "trilinear": 1}
 
 # name -> (restype, argtypes); mirrors include/ovfem.h
 _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -41,6 +42,7 @@ SIGNATURES = {
     "ovfem_get_step": (_i32, [_vp, ctypes.POINTER(_i64)]),
     "ovfem_set_checkpointing": (_i32, [_vp, _i64, _i64]),
     "ovfem_adjoint": (_i32, [_vp, _vp, _vp, _vp]),
+    "ovfem_set_element": (_i32, [_vp, _i32]),
     "ovfem_set_damping": (_i32, [_vp, _f64, _f64]),
     "ovfem_set_stages": (_i32, [_vp, _i32]),
     "ovfem_get_stages": (_i32, [_vp, ctypes.POINTER(_i32)]),
@@ -178,8 +180,10 @@ class Solver:
         self.n_rec, self.rec_nt = int(na.size), int(nt_max)
 
     @classmethod
-    def from_workload(cls, wl, precision="fp64", receivers_nt=None):
+    def from_workload(cls, wl, precision="fp64", receivers_nt=None, element="ovfem"):
         s = cls(wl.nx, wl.ny, wl.nz, wl.h, precision=precision, n_shots=wl.n_shots)
+        if element != "ovfem":
+            s.set_element(element)
         s.set_model(wl.lam, wl.mu, wl.rho, wl.solid)
         s.set_fixed_nodes(wl.fixed)
         s.set_dt(wl.dt)
@@ -246,6 +250,10 @@ class Solver:
         v = ctypes.c_int64()
         _check(_LIB.ovfem_get_step(self._h, ctypes.byref(v)))
         return v.value
+
+    # --- element type (before the model)
+    def set_element(self, element):
+        _check(_LIB.ovfem_set_element(self._h, ELEMENTS[element]))
 
     # --- Rayleigh damping C = alpha M + beta K
     def set_damping(self, alpha, beta):

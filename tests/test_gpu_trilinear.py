@@ -1,0 +1,97 @@
+"""GPU: the trilinear comparison element ("VFEM" of Sec. 2/3) on every path, against the
+oracle's trilinear stepper, matvec and adjoint."""
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from oracle import element as el
+from paper_2404_13683_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "int8", "int8-bf16"]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _solver(w, prec):
+    from paper_2404_13683_amd.ovfem import Solver
+    return Solver.from_workload(w, precision=prec, element="trilinear")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_trilinear_matvec(prec):
+    import torch
+    w = wl.layered_c2(nx=33, ny=29, nz=21, nt=10, seed=51)
+    u = wl.random_field((w.nz + 1, w.ny + 1, w.nx + 1, 3), seed=52)
+    ref = oasm.matvec(u, w.lam, w.mu, w.h, el.trilinear_reference())
+    s = _solver(w, prec)
+    got = s.matvec(torch.from_numpy(u.reshape(-1)).cuda()).cpu().numpy().reshape(u.shape)
+    err = _rel(got, ref)
+    print("trilinear matvec %s: %.3e" % (prec, err))
+    assert err <= 1e-12
+    # a different operator from OVFEM's
+    assert _rel(ref, oasm.matvec(u, w.lam, w.mu, w.h)) > 1e-2
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_trilinear_traces(prec):
+    w = wl.homogeneous_c1()
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt, element="trilinear")
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    s = _solver(w, prec)
+    s.step(w.nt)
+    et = _rel(s.get_traces().cpu().numpy()[0], ref)
+    eu = _rel(s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape), u_ref)
+    print("trilinear C1 %s: traces %.3e wavefield %.3e" % (prec, et, eu))
+    assert et <= 1e-9 and eu <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8"])
+def test_trilinear_adjoint_matches_the_oracle(prec):
+    import torch
+    nx, ny, nz, nt = 12, 10, 9, 50
+    rng = np.random.default_rng(53)
+    shape = (nz, ny, nx)
+    rho = rng.uniform(1900, 2400, shape)
+    vs = rng.uniform(500, 1100, shape)
+    lam, mu = wl.lame_from_velocities(2.0 * vs, vs, rho)
+    h = 4.0
+    dt = wl.stable_dt(h, lam * 1.2, mu * 1.2, rho)
+    src = np.array([wl.node_id(nx // 2, ny // 2, nz, nx, ny)], np.int64)
+    rec = wl.surface_nodes(rng, 5, nx, ny, nz, exclude=src)
+    w = wl.Workload("tri-adjoint", nx, ny, nz, h, lam, mu, rho, wl.box_fixed(nx, ny, nz), dt, nt, src,
+                    np.array([2], np.int32), np.array([0], np.int32), wl.ricker(nt, dt, 1.0 / (18 * dt))[None, :], rec)
+    mt = oasm.Model(lam * (1 + 0.1 * rng.standard_normal(shape)), mu, rho, h, w.fixed, dt, element="trilinear")
+    d_obs, *_ = oasm.simulate(mt, nt, src, w.src_comp, w.wavelet, rec)
+    m = oasm.Model(lam, mu, rho, h, w.fixed, dt, element="trilinear")
+    _, gl_ref, gm_ref = oasm.adjoint_gradient(m, nt, src, w.src_comp, w.wavelet, rec, d_obs)
+    s = _solver(w, prec)
+    s.set_checkpointing(9, nt)
+    s.step(nt)
+    res = (s.get_traces() - torch.from_numpy(d_obs).cuda()[None]).contiguous()
+    g_lam, g_mu = (g.cpu().numpy() for g in s.adjoint(res))
+    el_, em_ = _rel(g_lam, gl_ref), _rel(g_mu, gm_ref)
+    print("trilinear adjoint %s: %.3e %.3e" % (prec, el_, em_))
+    assert el_ <= 1e-9 and em_ <= 1e-9
+
+
+def test_element_switch_clears_the_model():
+    from paper_2404_13683_amd.ovfem import OvfemError, Solver
+    w = wl.homogeneous_c1(nx=6, ny=6, nz=6, nt=10)
+    s = Solver.from_workload(w, precision="fp64")
+    with pytest.raises(OvfemError):
+        _bad_element(s)
+    s.set_element("trilinear")
+    with pytest.raises(OvfemError):
+        s.step(1)  # model and dt must be set again
+    s.set_model(w.lam, w.mu, w.rho)
+    s.set_dt(w.dt)
+    s.step(1)
+
+
+def _bad_element(s):
+    from paper_2404_13683_amd import ovfem
+    ovfem._check(ovfem.lib().ovfem_set_element(s._h, 7))
