@@ -57,3 +57,24 @@ def test_highest_lattice_frequency_gives_cfl_h_over_vp():
     h = 1.0
     w = dsp.max_frequency(_ovfem(h), RHO, h, n=8)
     assert w == pytest.approx(2 * VP / h, rel=1e-12)
+
+
+def test_equal_dispersion_accuracy_fixture():
+    """tests/golden/equal_dispersion_accuracy.json is what the oracle computes, OVFEM is
+    the more accurate element at equal resolution, and both errors fall at second order."""
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(here, "make_equal_dispersion_accuracy.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    fx = json.load(open(os.path.join(here, "equal_dispersion_accuracy.json")))
+    rows = {r["ppw_ovfem"]: r for r in fx["rows"]}
+    dirs = mk.directions()
+    again = mk.equal_accuracy(10, dirs, iters=40)
+    for k in ("rms_phase_error", "ppw_trilinear", "cost_factor"):
+        assert again[k] == pytest.approx(rows[10][k], rel=1e-12)
+    assert rows[10]["ppw_trilinear"] > 10 and rows[10]["cost_factor"] > 1
+    assert rows[5]["rms_phase_error"] / rows[10]["rms_phase_error"] == pytest.approx(4.0, rel=0.1)
+    assert rows[10]["rms_phase_error"] / rows[20]["rms_phase_error"] == pytest.approx(4.0, rel=0.02)
