@@ -21,6 +21,11 @@
  *     INT32 accumulation; OVFEM_INT8_BF16 accumulates two digits per FP32 accumulator
  *     on bf16 matrix cores (every operand and partial sum is an integer that bf16 and
  *     FP32 represent exactly).
+ *   - OVFEM_FP64_SF evaluates the same element products in FP64 without the dense
+ *     24 x 24 matrices: the octant basis makes every psi-weighted displacement gradient
+ *     of Eq. (5) a scaled Walsh coefficient of the 8 corner values, so K_e u_e is two
+ *     8-point butterflies around a small stress evaluation (~250 instead of 2304 flops
+ *     per element).  A stronger FP64 baseline than the dense "as is" form of Sec. 3.
  *
  * Grid layout (shared by every array argument):
  *   elements e = i + nx (j + ny k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
@@ -63,6 +68,7 @@ typedef int32_t ovfem_status;
 #define OVFEM_FP64 0
 #define OVFEM_INT8 1      /* INT8 digit slices, int8 matrix cores, INT32 accumulation */
 #define OVFEM_INT8_BF16 2 /* INT8 digit slices, bf16 matrix cores, exact FP32 digit-pair sums */
+#define OVFEM_FP64_SF 3   /* FP64, the OVFEM element product sum-factorised (OVFEM element only) */
 
 /* limits */
 #define OVFEM_MAX_SHOTS 4096 /* shots per solver */
@@ -92,8 +98,9 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
 /* Free every device buffer of the solver (waits for its stream).  NULL is accepted. */
 ovfem_status ovfem_destroy(ovfem_solver* s);
 
-/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_BF16).
- * EINVAL for OVFEM_INT8_BF16 while the stage count (ovfem_set_stages) is not 8. */
+/* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_BF16 /
+ * OVFEM_FP64_SF).  EINVAL for OVFEM_INT8_BF16 while the stage count (ovfem_set_stages)
+ * is not 8, and for OVFEM_FP64_SF with the trilinear element. */
 ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision);
 
 /* Per-element material, HOST arrays of nx*ny*nz float64: Lame lam, shear modulus mu,

@@ -80,7 +80,9 @@ static_assert((long long)kMaxRowAbs * 128 * 257 < 2147483647LL, "digit-pair sums
 enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
 // PATH_INT8: digits on i8 matrix cores, INT32 accumulation with a shift per pair;
 // PATH_BF16: digit pairs on bf16 matrix cores, exact FP32 accumulation.
-enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_BF16 = 2 };
+// PATH_FP64SF: the OVFEM element product in FP64, sum-factorised (element_sf).
+enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_BF16 = 2, PATH_FP64SF = 3 };
+constexpr bool is_f64_path(int p) { return p == PATH_FP64 || p == PATH_FP64SF; }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -281,6 +283,84 @@ __device__ inline void element_fp64(const double ue[24], double lam_s, double mu
   }
 }
 
+// Sum-factorised OVFEM element product, y = K_e u_e with K_e = lam_h K_lam + mu_h K_mu
+// (lam_h = h lam_e, mu_h = h mu_e); the same operator as element_fp64<0>, rewritten
+// without approximation.  The gradient of the octant basis (Eq. (7)) is a difference
+// across a mid-plane, so every psi-weighted displacement gradient of Eq. (5) is a
+// scaled Walsh coefficient of the 8 corner values: with chi_S(alpha) = prod_{k in S}
+// rbar_k(alpha) and W_i[S] = sum_alpha chi_S(alpha) u_{alpha,i},
+//     (psi^b, d_j u_i)_e = (1/4) (1/2)^|b| W_i[b + {j}]     (j not in b),
+// b the set of axes where the stress monomial psi^b of Eq. (8) has exponent 1.  With
+// (psi^b psi^b)_e = 3^-|b| (h = 1) and the isotropic stress of the symmetric gradient,
+//     y_{alpha,c} = sum_S chi_S(alpha) V_c[S],
+//     V_c[S] = sum over (b, j not in b, b + {j} = S) of (1/16)(3/4)^|b| s_b(c, j),
+//     s_b(c, j) = lam_h tr_b delta_cj + mu_h (W_c[b + {j}] + W_j[b + {c}]),
+//     tr_b = sum_{i not in b} W_i[b + {i}].
+// Both transforms are 3-level butterflies: about 250 flops per element instead of the
+// 2304 of the dense product.
+__device__ inline void element_sf(const double ue[24], double lam_h, double mu_h, double y[24]) {
+  double W[3][8];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) W[i][a] = ue[3 * a + i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!((a >> k) & 1)) {
+          const double lo = W[i][a], hi = W[i][a | (1 << k)];
+          W[i][a] = lo + hi;            // k not in S
+          W[i][a | (1 << k)] = hi - lo;  // k in S: rbar_k = +1 at bit 1, -1 at bit 0
+        }
+  }
+  double V[3][8];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) V[i][a] = 0.0;
+  const double f0 = 1.0 / 16.0, f1 = f0 * 0.75, f2 = f1 * 0.75;
+  const double lb[3] = {lam_h * f0, lam_h * f1, lam_h * f2}, mb[3] = {mu_h * f0, mu_h * f1, mu_h * f2};
+  // the seven stress monomials: b = {}, {0}, {1}, {2}, {0,1}, {1,2}, {0,2}
+  constexpr int kB[7] = {0, 1, 2, 4, 3, 6, 5};
+#pragma unroll
+  for (int ib = 0; ib < 7; ++ib) {
+    const int b = kB[ib];
+    const int nb = (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1);
+    double tr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (!((b >> i) & 1)) tr += W[i][b | (1 << i)];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if ((b >> j) & 1) continue;
+      const int S = b | (1 << j);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double g = W[c][S];                            // (psi^b, d_j u_c) up to the factor
+        if (!((b >> c) & 1)) g += W[j][b | (1 << c)];  // + (psi^b, d_c u_j)
+        double sig = mb[nb] * g;
+        if (c == j) sig = fma(lb[nb], tr, sig);
+        V[c][S] += sig;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 2; k >= 0; --k)
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!((a >> k) & 1)) {
+          const double v0 = V[c][a], v1 = V[c][a | (1 << k)];
+          V[c][a] = v0 - v1;            // rbar_k = -1
+          V[c][a | (1 << k)] = v0 + v1;  // rbar_k = +1
+        }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) y[3 * a + c] = V[c][a];
+  }
+}
+
 // v of the lane one to the left within its row of 16 lanes (0 for the first lane).
 __device__ inline double row_shift_right(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x111, 0xf, 0xf, false);
@@ -340,15 +420,16 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   __shared__ double lsum[TE * 3 * TE];  // [q][c][p], q = 0..15
   __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
   __shared__ double red[4];
-  __shared__ __attribute__((aligned(16))) double matl[PATH == PATH_FP64 ? 2 : 2 * NTHR];  // slices: [b][a] material
-  constexpr int RING_BYTES = PATH == PATH_FP64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * St::PLANE * 4);
+  constexpr bool F64 = is_f64_path(PATH);
+  __shared__ __attribute__((aligned(16))) double matl[F64 ? 2 : 2 * NTHR];  // slices: [b][a] material
+  constexpr int RING_BYTES = F64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * St::PLANE * 4);
   __shared__ __attribute__((aligned(16))) unsigned char ring_raw[RING_BYTES];
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
 
   // ---- tile exponent (INT8): max over the 27 tiles owning the staged nodes
   int E = 0;
-  if (PATH != PATH_FP64) {
+  if (!F64) {
     int e = EXP_NONE;
     for (int dz = -1; dz <= 1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
@@ -427,7 +508,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     mat_next = load_material(mat_base + (size_t)(z_ok ? k : 0) * layer_bytes, elem, z_ok);
   };
   auto stage = [&](int slot) {
-    if (PATH == PATH_FP64) {
+    if (F64) {
       double* P = ringf + slot * FPLANE;
 #pragma unroll
       for (int c = 0; c < 3; ++c) P[(c * PN + mq) * PN + mp] = u_main_next.v[c];
@@ -457,7 +538,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     u_own_top = u_main_next;
     stage(top);
     const double2 mat_e = mat_next;
-    if (PATH != PATH_FP64) {
+    if (!F64) {
       matl[2 * t] = mat_e.x;
       matl[2 * t + 1] = mat_e.y;
     }
@@ -490,7 +571,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     __syncthreads();
 
     // ---- element layer k -> in-plane sums for plane k
-    if (PATH == PATH_FP64) {
+    if (F64) {
       double y[24];
       if (layer_ok) {
         const double* Pb = ringf + bot * FPLANE;
@@ -503,7 +584,10 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 #pragma unroll
           for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PN + tb + dj) * PN + ta + di];
         }
-        element_fp64<ELEM>(ue, mat_e.x, mat_e.y, y);
+        if constexpr (PATH == PATH_FP64SF)
+          element_sf(ue, mat_e.x * 256.0, mat_e.y * 128.0, y);  // mat holds h lam / 256, h mu / 128
+        else
+          element_fp64<ELEM>(ue, mat_e.x, mat_e.y, y);
       } else {
 #pragma unroll
         for (int i = 0; i < 24; ++i) y[i] = 0.0;
@@ -687,7 +771,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 // *step_base + step (step_base may be null), so a captured sequence of launches can
 // be replayed with a step base kept in device memory.
 template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
+__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
     ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
   layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
@@ -699,7 +783,7 @@ __global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
 // size is then a multiple of 8, so a work-group stays on one XCD's run).  The unit's
 // own step offset is units[u].step.
 template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, PATH == PATH_FP64 ? 1 : 2)
+__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
     ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                        const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;

@@ -153,7 +153,9 @@ std::vector<uint64_t> make_alane_i8(int elem) {
   return out;
 }
 
-bool valid_precision(int p) { return p == OVFEM_FP64 || p == OVFEM_INT8 || p == OVFEM_INT8_BF16; }
+bool valid_precision(int p) {
+  return p == OVFEM_FP64 || p == OVFEM_INT8 || p == OVFEM_INT8_BF16 || p == OVFEM_FP64_SF;
+}
 
 // Element-product form: precision and, for OVFEM_INT8, the digit stage count.
 struct Form {
@@ -180,6 +182,8 @@ void launch_unit_form(Form f, const KArgs& A, const long long* base, long long s
       case 7: ovfem_layer_kernel<PATH_INT8, MODE, 7, D><<<grid, block, 0, stream>>>(A, base, step); break;
       default: ovfem_layer_kernel<PATH_INT8, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step); break;
     }
+  } else if (f.precision == OVFEM_FP64_SF) {
+    ovfem_layer_kernel<PATH_FP64SF, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
   } else {
     ovfem_layer_kernel<PATH_BF16, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
   }
@@ -217,6 +221,8 @@ void launch_units_form(Form f, dim3 g, const KArgs* units, const int* begin, int
       case 7: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 7, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
       default: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
     }
+  } else if (f.precision == OVFEM_FP64_SF) {
+    ovfem_batch_kernel<PATH_FP64SF, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
   } else {
     ovfem_batch_kernel<PATH_BF16, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
   }
@@ -726,6 +732,8 @@ ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision) {
     require(valid_precision(precision), "ovfem_set_precision: unknown precision");
     require(precision != OVFEM_INT8_BF16 || s->stages == 8,
             "ovfem_set_precision: OVFEM_INT8_BF16 runs 8 digit stages only (call ovfem_set_stages(s, 8) first)");
+    require(precision != OVFEM_FP64_SF || s->element == OVFEM_ELEMENT_OVFEM,
+            "ovfem_set_precision: OVFEM_FP64_SF is the OVFEM element's factorisation");
     s->precision = precision;
   });
 }
@@ -923,7 +931,7 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
     A.ku = Ku;
     A.src_nt = 0;
     A.rec_nt = 0;
-    if (s->precision != OVFEM_FP64) {
+    if (s->precision == OVFEM_INT8 || s->precision == OVFEM_INT8_BF16) {
       s->launch_exponents(s->geom, u, s->expo_tmp.p, 1);
       A.exp_in = s->expo_tmp.p;
     }
@@ -981,6 +989,8 @@ ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_element: solver is NULL");
     require(element == OVFEM_ELEMENT_OVFEM || element == OVFEM_ELEMENT_TRILINEAR, "ovfem_set_element: unknown element");
+    require(element == OVFEM_ELEMENT_OVFEM || s->precision != OVFEM_FP64_SF,
+            "ovfem_set_element: OVFEM_FP64_SF is the OVFEM element's factorisation");
     s->check_device();
     if (element == s->element) return;
     DevBuf<uint32_t> bf;

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libovfem.so")
 OVFEM_FP64 = 0
 OVFEM_INT8 = 1
 OVFEM_INT8_BF16 = 2
-PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8, "int8-bf16": OVFEM_INT8_BF16}
+OVFEM_FP64_SF = 3
+PRECISIONS = {"fp64": OVFEM_FP64, "int8": OVFEM_INT8, "int8-bf16": OVFEM_INT8_BF16, "fp64-sf": OVFEM_FP64_SF}
 ELEMENTS = {"ovfem": 0, "trilinear": 1}
 
 # name -> (restype, argtypes); mirrors include/ovfem.h

@@ -14,7 +14,7 @@ from paper_2404_13683_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "int8", "int8-bf16"]
+PRECS = ["fp64", "int8", "int8-bf16", "fp64-sf"]
 TRACE_TOL = 1e-9
 
 

@@ -124,7 +124,7 @@ def run_pair(w, steps, check_state_after=None):
     """Both paths over `steps` steps (autotuned launch configuration); returns traces."""
     from paper_2404_13683_amd.ovfem import Solver
     out = {}
-    for prec in ("fp64", "int8"):
+    for prec in ("fp64", "int8", "fp64-sf"):
         s = Solver.from_workload(w, precision=prec, receivers_nt=steps + 1)
         s.autotune(steps=6)
         check_matvec_sampled(w, s, prec)
@@ -134,9 +134,10 @@ def run_pair(w, steps, check_state_after=None):
         if check_state_after:
             check_one_step_sampled(w, s, prec)
         s.close()
-    err = _rel(out["int8"], out["fp64"])
-    print("%s INT8 vs FP64 traces over %d steps: rel L2 %.3e" % (w.name, steps, err))
-    assert err <= TRACE_TOL
+    for p in ("int8", "fp64-sf"):
+        err = _rel(out[p], out["fp64"])
+        print("%s %s vs FP64 traces over %d steps: rel L2 %.3e" % (w.name, p, steps, err))
+        assert err <= TRACE_TOL
     return out
 
 

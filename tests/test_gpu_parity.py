@@ -11,7 +11,7 @@ from paper_2404_13683_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "int8", "int8-bf16"]
+PRECS = ["fp64", "int8", "int8-bf16", "fp64-sf"]
 MATVEC_TOL = 1e-12
 TRACE_TOL = 1e-9
 
@@ -129,6 +129,8 @@ def test_int8_not_less_accurate_than_fp64():
                 errs[p].append(abs(float(Fraction(float(got[p][k, j, i, c])) - exact[c])) / abs(float(exact[c])))
     med = {p: float(np.median(errs[p])) for p in PRECS}
     print("median rel error vs exact:", med)
+    # the factorised FP64 product rounds differently but to FP64 accuracy
+    assert med["fp64-sf"] < 1e-15 and max(errs["fp64-sf"]) < 1e-13
     for p in ("int8", "int8-bf16"):
         assert med[p] <= med["fp64"]
         assert max(errs[p]) < 1e-13
