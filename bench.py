@@ -268,6 +268,7 @@ def main():
     if "fp64-sf" in res:
         f = res["fp64-sf"]
         out["fp64_sf_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"],
+                               "traffic": measured_traffic("fp64-sf") if args.workload == "c2" else None,
                                "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK, "tuning": f["tuning"],
                                "note": "the OVFEM product sum-factorised in FP64 (a stronger FP64 baseline than the "
                                        "dense form the paper compares against)"}
