@@ -127,6 +127,13 @@ struct KArgs {
   // acoef = dt^2 / (m (1 + alpha dt / 2)).  unext must then not alias uprev (the halo
   // of u^{n-1} is read by neighbouring work-groups).
   double damp_b, damp_c1, damp_c2;
+  // shots of one grid in one launch (ovfem_layer_kernel): n_units units of n_wg tiles,
+  // unit v at these element offsets from the pointers above (0 units taken as 1)
+  int n_units;
+  long long unit_u;    // nodal vectors: u, uprev, unext
+  int unit_exp;        // exp_in, exp_out
+  int unit_src;        // src_ptr
+  long long unit_tr;   // traces
 };
 
 // Logical tile of this work-group.  Work-groups are dealt to the 8 XCDs round-robin
@@ -767,14 +774,27 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   if (MODE == MODE_STEP) write_tile_exponent(tile_max, A.exp_out + wg, red);
 }
 
-// One unit (one shot of one grid): one work-group per tile.  The step index is
-// *step_base + step (step_base may be null), so a captured sequence of launches can
-// be replayed with a step base kept in device memory.
+// The shots of one grid (A.n_units of them, laid out at fixed strides): one work-group
+// per tile and shot, work items remapped so each XCD takes a contiguous run.  The step
+// index is *step_base + step (step_base may be null), so a captured sequence of launches
+// can be replayed with a step base kept in device memory.
 template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
 __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
     ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
-  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, logical_tile(blockIdx.x, A.g.n_wg), s);
+  const int units = A.n_units > 1 ? A.n_units : 1;
+  const int item = logical_tile(blockIdx.x, A.g.n_wg * units);
+  const int v = item / A.g.n_wg;
+  if (v > 0) {
+    A.u += v * A.unit_u;
+    A.uprev += v * A.unit_u;
+    A.unext += v * A.unit_u;
+    A.exp_in += v * A.unit_exp;
+    A.exp_out += v * A.unit_exp;
+    A.src_ptr += v * A.unit_src;
+    A.traces += v * A.unit_tr;
+  }
+  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, item - v * A.g.n_wg, s);
 }
 
 // Many units in one launch (the shots of a grid, or grids of uneven size): unit u owns

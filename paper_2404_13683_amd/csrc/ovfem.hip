@@ -168,7 +168,7 @@ struct Form {
 // One unit, one work-group per tile.
 template <int MODE, bool D>
 void launch_unit_form(Form f, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
-  const dim3 grid(A.g.n_wg), block(NTHR);
+  const dim3 grid(A.g.n_wg * (A.n_units > 1 ? A.n_units : 1)), block(NTHR);
   if (f.precision == OVFEM_FP64) {
     if (f.elem == OVFEM_ELEMENT_TRILINEAR)
       ovfem_layer_kernel<PATH_FP64, MODE, 8, D, 1><<<grid, block, 0, stream>>>(A, base, step);
@@ -524,13 +524,22 @@ struct ovfem_solver {
     tables_dirty = false;
   }
 
-  // one step of every shot at phase ph; step index *base + step_arg
+  // one step of every shot at phase ph; step index *base + step_arg.  The shots of the
+  // grid share one argument record with per-shot strides, unless a grid cap asks for
+  // the striding work-list kernel.
   void launch_step(hipStream_t st, int ph, const long long* base, long long step_arg) {
-    if (n_shots == 1)
-      launch_unit<MODE_STEP>(form(), shot_args(0, ph), base, step_arg, st);
-    else
+    if (n_shots == 1 || persist_groups == 0) {
+      KArgs A = shot_args(0, ph);
+      A.n_units = n_shots;
+      A.unit_u = (long long)vec();
+      A.unit_exp = geom.n_wg;
+      A.unit_src = geom.n_wg + 1;
+      A.unit_tr = (long long)n_rec * 3 * rec_nt;
+      launch_unit<MODE_STEP>(form(), A, base, step_arg, st);
+    } else {
       launch_units(form(), units.p + (size_t)ph * n_shots, unit_begin.p, n_shots, n_shots * geom.n_wg,
                    persist_groups, base, step_arg, st);
+    }
   }
 
   // capture graph_steps (even) undamped steps starting at phase p, followed by the
