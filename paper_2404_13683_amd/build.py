@@ -9,15 +9,15 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ovfem.hip")
+CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libovfem.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 
-HIPCC_FLAGS = [
+COMPILE_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # the reference matrices are derived by constexpr evaluation of the element integrals
     "-fconstexpr-steps=100000000",
     # no packed FP32 instructions in any generated code
@@ -26,6 +26,13 @@ HIPCC_FLAGS = [
     "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
 ]
+# kept for callers that build single sources by hand
+HIPCC_FLAGS = COMPILE_FLAGS + ["-shared"]
+
+
+def sources():
+    """Translation units: the host library and one per kernel instantiation group."""
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def hipcc():
@@ -35,15 +42,41 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False):
-    """Compile libovfem.so; always recompiles.  Returns the library path."""
+def _messages(res):
+    return [ln for ln in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+
+
+def build(verbose=False, jobs=None):
+    """Compile libovfem.so; always recompiles (the translation units in parallel).
+    Returns the library path."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    jobs = jobs or max(1, min(len(sources()), os.cpu_count() or 1, 16))
+    cc = hipcc()
+    pending, objs, msgs = list(sources()), [], []
+    running = []
+    while pending or running:
+        while pending and len(running) < jobs:
+            src = pending.pop(0)
+            obj = os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
+            cmd = [cc] + COMPILE_FLAGS + ["-c", "-o", obj, src]
+            running.append((src, obj, subprocess.Popen(cmd, cwd=HERE, stdout=subprocess.PIPE,
+                                                       stderr=subprocess.PIPE, text=True)))
+        src, obj, proc = running.pop(0)
+        out, err = proc.communicate()
+        m = [ln for ln in (out + err).splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+        if proc.returncode != 0:
+            for _, _, p in running:
+                p.kill()
+            raise RuntimeError("hipcc failed on %s:\n%s" % (os.path.basename(src), "\n".join(m)))
+        msgs += m
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp, SRC]
-    res = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)
-    msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
-            if "packed-fp32-ops" not in ln and ln.strip()]
+    res = subprocess.run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + sorted(objs), cwd=HERE,
+                         capture_output=True, text=True)
+    m = _messages(res)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
+        raise RuntimeError("link failed:\n" + "\n".join(m))
+    msgs += m
     if verbose and msgs:
         print("\n".join(msgs), file=sys.stderr)
     os.replace(tmp, LIB)

@@ -797,38 +797,55 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
   layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, item - v * A.g.n_wg, s);
 }
 
-// Many units in one launch (the shots of a grid, or grids of uneven size): unit u owns
-// work items [unit_begin[u], unit_begin[u+1]).  Work items are remapped so that each XCD
-// gets a contiguous run; a grid smaller than the work list strides over it (the grid
-// size is then a multiple of 8, so a work-group stays on one XCD's run).  The unit's
-// own step offset is units[u].step.
+// Many units in one launch (grids of uneven size, each with its shots): unit u owns work
+// items [unit_begin[u], unit_begin[u+1]) and is found by binary search; its own step
+// offset is units[u].step.  Work items are remapped so that each XCD gets a contiguous
+// run.  ovfem_batch_kernel takes one work item per work-group;
+// ovfem_batch_strided_kernel runs on a grid smaller than the work list and strides over
+// it (the grid size is then a multiple of 8, so a work-group stays on one XCD's run).
+__device__ inline int find_unit(const int* unit_begin, int n_units, int item) {
+  int lo = 0, hi = n_units - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (unit_begin[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
 __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
     ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                        const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
+  const int item = logical_tile(blockIdx.x, total);
+  const int v = find_unit(unit_begin, n_units, item);
+  const KArgs A = units[v];
+  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, item - unit_begin[v], s + A.step);
+}
+
+template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
+__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
+    ovfem_batch_strided_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
+                               const long long* step_base, long long step) {
+  const long long s = (step_base ? *step_base : 0) + step;
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const int item = logical_tile(b, total);
-    int lo = 0, hi = n_units - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (unit_begin[mid] <= item) lo = mid;
-      else hi = mid - 1;
-    }
-    const KArgs A = units[lo];
-    layer_tile<PATH, MODE, M, DAMP, false, ELEM>(A, item - unit_begin[lo], s + A.step);
+    const int v = find_unit(unit_begin, n_units, item);
+    const KArgs A = units[v];
+    layer_tile<PATH, MODE, M, DAMP, false, ELEM>(A, item - unit_begin[v], s + A.step);
     __syncthreads();  // LDS is reused by the next work item
   }
 }
 
 // Adds n to the device step base (last node of a captured block of steps).
-__global__ void ovfem_advance_step_kernel(long long* step_base, long long n) {
+static __global__ void ovfem_advance_step_kernel(long long* step_base, long long n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
 }
 
 // Tile exponents of a nodal vector u, or with up of u + b (u - up) (the vector a damped
 // step stages), in the stepper's tiling.
-__global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const double* u, const double* up, double b,
+static __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const double* u, const double* up, double b,
                                                                int* exp_out) {
   __shared__ double red[4];
   const int wg = blockIdx.x;

@@ -1,0 +1,8 @@
+// Kernel instantiations: PATH_INT8, 5, 0.
+#include "launch_impl.hpp"
+
+namespace ovfem {
+
+OVFEM_DEFINE_LAUNCHERS(PATH_INT8, 5, 0)
+
+}  // namespace ovfem

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
+#include "launch.hpp"
 #include "ovfem.h"
 
 using namespace ovfem;
@@ -165,76 +165,56 @@ struct Form {
   int elem;   // OVFEM_ELEMENT_*: selects the FP64 path's compile-time element matrices
 };
 
-// One unit, one work-group per tile.
-template <int MODE, bool D>
-void launch_unit_form(Form f, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
-  const dim3 grid(A.g.n_wg * (A.n_units > 1 ? A.n_units : 1)), block(NTHR);
-  if (f.precision == OVFEM_FP64) {
-    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
-      ovfem_layer_kernel<PATH_FP64, MODE, 8, D, 1><<<grid, block, 0, stream>>>(A, base, step);
-    else
-      ovfem_layer_kernel<PATH_FP64, MODE, 8, D, 0><<<grid, block, 0, stream>>>(A, base, step);
-  } else if (f.precision == OVFEM_INT8) {
-    switch (f.stages) {
-      case 4: ovfem_layer_kernel<PATH_INT8, MODE, 4, D><<<grid, block, 0, stream>>>(A, base, step); break;
-      case 5: ovfem_layer_kernel<PATH_INT8, MODE, 5, D><<<grid, block, 0, stream>>>(A, base, step); break;
-      case 6: ovfem_layer_kernel<PATH_INT8, MODE, 6, D><<<grid, block, 0, stream>>>(A, base, step); break;
-      case 7: ovfem_layer_kernel<PATH_INT8, MODE, 7, D><<<grid, block, 0, stream>>>(A, base, step); break;
-      default: ovfem_layer_kernel<PATH_INT8, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step); break;
-    }
-  } else if (f.precision == OVFEM_FP64_SF) {
-    ovfem_layer_kernel<PATH_FP64SF, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
-  } else {
-    ovfem_layer_kernel<PATH_BF16, MODE, 8, D><<<grid, block, 0, stream>>>(A, base, step);
-  }
-}
+// One record, one work-group per tile (and shot).
 template <int MODE>
 void launch_unit(Form f, const KArgs& A, const long long* base, long long step, hipStream_t stream) {
-  if constexpr (MODE == MODE_STEP) {
-    if (f.damp)
-      launch_unit_form<MODE_STEP, true>(f, A, base, step, stream);
+  const bool d = MODE == MODE_STEP && f.damp;
+  if (f.precision == OVFEM_FP64) {
+    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
+      launch_tiles<PATH_FP64, 8, 1>(MODE, d, A, base, step, stream);
     else
-      launch_unit_form<MODE_STEP, false>(f, A, base, step, stream);
+      launch_tiles<PATH_FP64, 8, 0>(MODE, d, A, base, step, stream);
+  } else if (f.precision == OVFEM_INT8) {
+    switch (f.stages) {
+      case 4: launch_tiles<PATH_INT8, 4, 0>(MODE, d, A, base, step, stream); break;
+      case 5: launch_tiles<PATH_INT8, 5, 0>(MODE, d, A, base, step, stream); break;
+      case 6: launch_tiles<PATH_INT8, 6, 0>(MODE, d, A, base, step, stream); break;
+      case 7: launch_tiles<PATH_INT8, 7, 0>(MODE, d, A, base, step, stream); break;
+      default: launch_tiles<PATH_INT8, 8, 0>(MODE, d, A, base, step, stream); break;
+    }
+  } else if (f.precision == OVFEM_FP64_SF) {
+    launch_tiles<PATH_FP64SF, 8, 0>(MODE, d, A, base, step, stream);
   } else {
-    launch_unit_form<MODE, false>(f, A, base, step, stream);
+    launch_tiles<PATH_BF16, 8, 0>(MODE, d, A, base, step, stream);
   }
   OVFEM_HIP(hipGetLastError());
 }
 
 // Many units in one launch; grid_cap > 0 caps the grid (rounded down to a multiple of
 // 8, at least 8) so that the work-groups stride over the work list.
-template <bool D>
-void launch_units_form(Form f, dim3 g, const KArgs* units, const int* begin, int n_units, int total,
-                       const long long* base, long long step, hipStream_t stream) {
-  const dim3 block(NTHR);
-  const auto U = units;
-  if (f.precision == OVFEM_FP64) {
-    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
-      ovfem_batch_kernel<PATH_FP64, MODE_STEP, 8, D, 1><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
-    else
-      ovfem_batch_kernel<PATH_FP64, MODE_STEP, 8, D, 0><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
-  } else if (f.precision == OVFEM_INT8) {
-    switch (f.stages) {
-      case 4: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 4, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
-      case 5: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 5, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
-      case 6: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 6, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
-      case 7: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 7, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
-      default: ovfem_batch_kernel<PATH_INT8, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step); break;
-    }
-  } else if (f.precision == OVFEM_FP64_SF) {
-    ovfem_batch_kernel<PATH_FP64SF, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
-  } else {
-    ovfem_batch_kernel<PATH_BF16, MODE_STEP, 8, D><<<g, block, 0, stream>>>(U, begin, n_units, total, base, step);
-  }
-}
 void launch_units(Form f, const KArgs* units, const int* begin, int n_units, int total, int grid_cap,
                   const long long* base, long long step, hipStream_t stream) {
   int grid = total;
   if (grid_cap > 0 && grid_cap < total) grid = std::max(8, (grid_cap / 8) * 8);
-  if (f.damp)
-    launch_units_form<true>(f, dim3(grid), units, begin, n_units, total, base, step, stream);
-  else
-    launch_units_form<false>(f, dim3(grid), units, begin, n_units, total, base, step, stream);
+  const bool d = f.damp;
+  if (f.precision == OVFEM_FP64) {
+    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
+      launch_list<PATH_FP64, 8, 1>(d, grid, units, begin, n_units, total, base, step, stream);
+    else
+      launch_list<PATH_FP64, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+  } else if (f.precision == OVFEM_INT8) {
+    switch (f.stages) {
+      case 4: launch_list<PATH_INT8, 4, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 5: launch_list<PATH_INT8, 5, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 6: launch_list<PATH_INT8, 6, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 7: launch_list<PATH_INT8, 7, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
+      default: launch_list<PATH_INT8, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
+    }
+  } else if (f.precision == OVFEM_FP64_SF) {
+    launch_list<PATH_FP64SF, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+  } else {
+    launch_list<PATH_BF16, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+  }
   OVFEM_HIP(hipGetLastError());
 }
 
