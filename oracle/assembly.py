@@ -200,10 +200,19 @@ def adjoint_gradient(model, nt, src_node, src_comp, wavelet, rec_node, d_obs, ck
         w^m = 2 w^{m+1} - w^{m+2} - A K w^{m+1} + A R^T r^{m-1},   m = N .. 1,
     with r^{n} = traces at step n minus d_obs, and
         dJ/dlam_e = - sum_{m=1}^{N} h (w_e^m)^T K_lam u_e^{m-1}   (same with K_mu).
+    With Rayleigh damping the recursion is u^{n+1} = P u^n + Q u^{n-1} + Ah F^n with
+    P = c1 I - (1+b) Ah K, Q = -c2 I + b Ah K (c1 = 2/(1+a), c2 = (1-a)/(1+a),
+    a = alpha dt/2, b = beta/dt, Ah = A/(1+a)); the same Lagrangian argument with
+    w = Ah lambda gives
+        w^m = c1 w^{m+1} - c2 w^{m+2} - Ah K ((1+b) w^{m+1} - b w^{m+2}) + Ah R^T r^{m-1},
+        dJ/dlam_e = - sum_m h (w_e^m)^T K_lam ((1+b) u^{m-1} - b u^{m-2})_e.
     Forward states are kept every ckpt_every steps and recomputed per segment
     (ckpt_every=None keeps all of them).
     Returns (J, g_lam, g_mu).
     """
+    damped = model.alpha != 0.0 or model.beta != 0.0
+    ad = 0.5 * model.alpha * model.dt
+    bd = model.beta / model.dt
     rec = np.asarray(rec_node, dtype=np.int64)
     nx, ny, nz = model.nx, model.ny, model.nz
     every = nt if ckpt_every is None else int(ckpt_every)
@@ -230,22 +239,29 @@ def adjoint_gradient(model, nt, src_node, src_comp, wavelet, rec_node, d_obs, ck
     seg_starts = sorted(ckpts.keys(), reverse=True)
     for s in seg_starts:
         e = min(s + every, nt)
-        # recompute u^s .. u^e from the checkpoint
+        # recompute u^s .. u^e from the checkpoint (states[0] = u^{s-1} when damped)
         u, up = ckpts[s]
-        states = [u.copy()]
+        states = ([up.copy()] if damped else []) + [u.copy()]
+        o = 1 if damped else 0
         for n in range(s, e):
             F = forcing(model.node_shape, src_node, src_comp, wavelet[:, n])
             un = model.step(u, up, F)
             up, u = u, un
             states.append(u.copy())
-        # adjoint steps m = e .. s+1 use u^{m-1} = states[m-1-s]
+        # adjoint steps m = e .. s+1 use u^{m-1} = states[m-1-s+o]
         for m in range(e, s, -1):
             src = np.zeros(model.node_shape)
             flat = src.reshape(-1, 3)
             np.add.at(flat, rec, resid[:, :, m - 1])
-            wm = 2.0 * w1 - w2 - A * model.K(w1) + A * src
+            if damped:
+                Ah = A / (1.0 + ad)
+                wm = (2.0 * w1 - (1.0 - ad) * w2) / (1.0 + ad) - Ah * model.K((1.0 + bd) * w1 - bd * w2) + Ah * src
+                uh = (1.0 + bd) * states[m - 1 - s + o] - bd * states[m - 2 - s + o]
+            else:
+                wm = 2.0 * w1 - w2 - A * model.K(w1) + A * src
+                uh = states[m - 1 - s]
             wm[~model.free] = 0.0
-            gl, gm = element_forms(gather(states[m - 1 - s], nx, ny, nz),
+            gl, gm = element_forms(gather(uh, nx, ny, nz),
                                    gather(wm, nx, ny, nz), model.h, model.Kref)
             g_lam -= gl
             g_mu -= gm

@@ -83,10 +83,13 @@ def test_finite_propagation_speed_one_node_per_step():
     assert d == nt - 1   # u^{n} is nonzero up to n-1 nodes away (F^0 enters u^1 locally)
 
 
-@pytest.mark.parametrize("element", ["ovfem", "trilinear"])
-def test_adjoint_gradient_matches_central_differences(element):
+@pytest.mark.parametrize("element,damping", [("ovfem", None), ("trilinear", None), ("ovfem", "rayleigh")])
+def test_adjoint_gradient_matches_central_differences(element, damping):
     m0, dt = _hetero_model(nx=5, ny=4, nz=4, seed=5)
-    m = asm.Model(m0.lam, m0.mu, m0.rho, m0.h, wl.box_fixed(m0.nx, m0.ny, m0.nz), dt, element=element)
+    # Rayleigh damping of ratio 0.05 at the wavelet's band (a fifth of dt for beta)
+    alpha, beta = (0.0, 0.0) if damping is None else (0.05 * 2 * np.pi / (20 * dt), 0.2 * dt)
+    m = asm.Model(m0.lam, m0.mu, m0.rho, m0.h, wl.box_fixed(m0.nx, m0.ny, m0.nz), dt, element=element,
+                  alpha=alpha, beta=beta)
     nx, ny, nz = m.nx, m.ny, m.nz
     nt = 60
     src = [wl.node_id(2, 2, nz, nx, ny)]
@@ -95,14 +98,14 @@ def test_adjoint_gradient_matches_central_differences(element):
     # synthetic observations from a perturbed model
     rng = np.random.default_rng(6)
     mt = asm.Model(m.lam * (1 + 0.1 * rng.standard_normal(m.lam.shape)), m.mu, m.rho, m.h,
-                   wl.box_fixed(nx, ny, nz), dt, element=element)
+                   wl.box_fixed(nx, ny, nz), dt, element=element, alpha=alpha, beta=beta)
     d_obs, *_ = asm.simulate(mt, nt, src, [2], w, rec)
     J, gl, gm = asm.adjoint_gradient(m, nt, src, [2], w, rec, d_obs)
     J2, gl2, gm2 = asm.adjoint_gradient(m, nt, src, [2], w, rec, d_obs, ckpt_every=7)
     assert J == J2 and np.array_equal(gl, gl2) and np.array_equal(gm, gm2)
 
     def J_of(lam, mu):
-        mm = asm.Model(lam, mu, m.rho, m.h, wl.box_fixed(nx, ny, nz), dt, element=element)
+        mm = asm.Model(lam, mu, m.rho, m.h, wl.box_fixed(nx, ny, nz), dt, element=element, alpha=alpha, beta=beta)
         tr, *_ = asm.simulate(mm, nt, src, [2], w, rec)
         return asm.misfit(tr, d_obs)
 
