@@ -179,6 +179,10 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
  *     w^{N+1} = w^{N+2} = 0,   w^m = 2 w^{m+1} - w^{m+2} + A (R^T r^{m-1} - K w^{m+1}),
  * which is the forward step with the residual injected at the receivers, and
  *     g_lam[e] = - sum_m h (w_e^m)^T K_lam u_e^{m-1}   (g_mu likewise with K_mu).
+ * With Rayleigh damping (ovfem_set_damping) the adjoint of the damped recursion takes
+ * the same form as the damped forward step (w = A lambda with A = dt^2 M^{-1} / (1 +
+ * alpha dt/2)) and u^{m-1} in the gradient becomes the staged (1+b) u^{m-1} - b u^{m-2},
+ * b = beta / dt.
  * Requires a forward run of N >= 1 steps from reset with checkpointing enabled, the same
  * precision, model and dt, and receivers recording every step (N <= nt_max).
  * residual: DEVICE float64 [receiver][component][nt_max] (the layout of the traces;
@@ -208,8 +212,8 @@ ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element);
  *                               + dt^2 M^{-1} (F^n - K (u^n + (beta/dt)(u^n - u^{n-1}))).
  * Its stability bound on dt shrinks to w_max^2 dt (dt + 2 beta) <= 4 (checked against
  * the element bound of w_max, as ovfem_set_dt does).  A damped solver keeps a third
- * nodal vector per shot, does not replay captured graphs, and has no adjoint (ESTATE);
- * damped and undamped solvers cannot share a batch.  Resets the wavefield.  EINVAL for
+ * nodal vector per shot and does not replay captured graphs; damped and undamped
+ * solvers cannot share a batch.  ovfem_adjoint differentiates the damped recursion.  Resets the wavefield.  EINVAL for
  * negative or non-finite values, or a dt already set that the new beta makes unstable. */
 ovfem_status ovfem_set_damping(ovfem_solver* s, double alpha, double beta);
 

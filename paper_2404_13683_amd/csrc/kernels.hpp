@@ -871,13 +871,14 @@ static __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, con
 
 // Per-element gradient terms of the discrete adjoint: for every solid element e,
 //     g_lam[e] -= h w_e^T K_lam u_e,   g_mu[e] -= h w_e^T K_mu u_e,
-// with u = u^{m-1} and w = w^m (the derivative of w^T K u with respect to lam_e, mu_e,
+// with u = u^{m-1} (with Rayleigh damping the staged (1+b) u^{m-1} - b u^{m-2}, b = beta/dt)
+// and w = w^m (the derivative of w^T K u with respect to lam_e, mu_e,
 // from K_e = h (lam_e K_lam + mu_e K_mu)).  One thread per element; each element's
 // sums are private, so the accumulation order is fixed.  ELEM: 0 OVFEM, 1 trilinear.
 template <int ELEM>
 __global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, const double* mat,
-                                                               const double* u, const double* w,
-                                                               double* g_lam, double* g_mu) {
+                                                               const double* u, const double* u2, double b,
+                                                               const double* w, double* g_lam, double* g_mu) {
   const long long e = (long long)blockIdx.x * NTHR + threadIdx.x;
   const long long ne = (long long)g.nx * g.ny * g.nz;
   if (e >= ne) return;
@@ -891,7 +892,8 @@ __global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, 
                         (long long)(g.nx + 1) * ((Y + ((alpha >> 1) & 1)) + (long long)(g.ny + 1) * (Z + (alpha >> 2)));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      ue[3 * alpha + c] = u[3 * n + c];
+      const double x = u[3 * n + c];
+      ue[3 * alpha + c] = u2 ? fma(b, x - u2[3 * n + c], x) : x;  // damped: the staged (1+b) u - b u2
       we[3 * alpha + c] = w[3 * n + c];
     }
   }

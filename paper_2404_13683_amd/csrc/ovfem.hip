@@ -1224,7 +1224,6 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
             "then step from reset without changing precision, tiling or wavefield)",
             OVFEM_ESTATE);
     require(n >= 1, "ovfem_adjoint: no forward steps to differentiate", OVFEM_ESTATE);
-    require(!s->damped(), "ovfem_adjoint: the adjoint of the damped recursion is not provided", OVFEM_ESTATE);
     require(s->n_rec > 0 && n <= s->rec_nt, "ovfem_adjoint: receivers must record every forward step", OVFEM_ESTATE);
     require(s->model_set && s->dt_set, "ovfem_adjoint: model and dt not set", OVFEM_ESTATE);
     s->refresh_acoef();
@@ -1258,15 +1257,20 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       upload(d_acomp, acomp, s->stream);
       upload(d_arow, arow, s->stream);
       seg.alloc((size_t)(every + 1) * vec);
-      wbuf.alloc(2 * vec);
+      const bool damped = s->damped();
+      const double bd = damped ? s->damp_b() : 0.0;
+      wbuf.alloc(3 * vec);
       fexp.alloc(2 * g.n_wg);
       wexp.alloc(2 * g.n_wg);
       OVFEM_HIP(hipMemsetAsync(g_lam, 0, s->n_elem * sizeof(double), s->stream));
       OVFEM_HIP(hipMemsetAsync(g_mu, 0, s->n_elem * sizeof(double), s->stream));
-      OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 2 * vec * sizeof(double), s->stream));
-      double* w[2] = {wbuf.p, wbuf.p + vec};
-      int wc = 0;  // w[wc] = w^{m+1}, w[wc ^ 1] = w^{m+2}; half wc of wexp: exponents of w[wc]
-      s->launch_exponents(g, w[0], wexp.p, 1);
+      OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 3 * vec * sizeof(double), s->stream));
+      // w[i1] = w^{m+1}, w[i2] = w^{m+2}; a step writes w^m over w^{m+2} (undamped) or
+      // into the third buffer (damped: the halo of w^{m+2} is read by neighbours); the
+      // exponent halves alternate, half we holding those of the next staged vector
+      double* w[3] = {wbuf.p, wbuf.p + vec, wbuf.p + 2 * vec};
+      int i1 = 0, i2 = 1, we = 0;
+      s->launch_exponents(g, w[i1], wexp.p, 1, damped ? w[i2] : nullptr, bd);
 
       KArgs F = s->shot_args(0, s->phase);  // forward recompute: forward sources, no recording
       F.rec_nt = 0;
@@ -1288,7 +1292,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           return seg.p + (size_t)k * vec;
         };
         int fe = 0;
-        s->launch_exponents(g, state(0), fexp.p, 1);
+        s->launch_exponents(g, state(0), fexp.p, 1, damped ? state(-1) : nullptr, bd);
         for (int64_t t = s0; t < e0; ++t) {
           F.u = state(t - s0);
           F.uprev = state(t - s0 - 1);
@@ -1299,19 +1303,24 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           fe ^= 1;
         }
         for (int64_t m = e0; m > s0; --m) {
-          B.u = w[wc];
-          B.uprev = w[wc ^ 1];
-          B.unext = w[wc ^ 1];
-          B.exp_in = wexp.p + wc * g.n_wg;
-          B.exp_out = wexp.p + (wc ^ 1) * g.n_wg;
+          const int inew = damped ? 3 - i1 - i2 : i2;
+          B.u = w[i1];
+          B.uprev = w[i2];
+          B.unext = w[inew];
+          B.exp_in = wexp.p + we * g.n_wg;
+          B.exp_out = wexp.p + (we ^ 1) * g.n_wg;
           launch_unit<MODE_STEP>(s->form(), B, nullptr, m - 1, s->stream);
-          wc ^= 1;
+          we ^= 1;
+          i2 = i1;
+          i1 = inew;
+          const double* u1 = state(m - 1 - s0);
+          const double* u2 = damped ? state(m - 2 - s0) : nullptr;
           if (s->element == OVFEM_ELEMENT_TRILINEAR)
-            ovfem_gradient_kernel<1><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc],
-                                                                      g_lam, g_mu);
+            ovfem_gradient_kernel<1><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, u1, u2, bd, w[i1], g_lam,
+                                                                      g_mu);
           else
-            ovfem_gradient_kernel<0><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, state(m - 1 - s0), w[wc],
-                                                                      g_lam, g_mu);
+            ovfem_gradient_kernel<0><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, u1, u2, bd, w[i1], g_lam,
+                                                                      g_mu);
           OVFEM_HIP(hipGetLastError());
         }
       }

@@ -146,10 +146,98 @@ def test_damping_validation():
     s.set_damping(10.0, 0.1 * w.dt)
     s.set_checkpointing(5, 20)
     s.step(20)
-    with pytest.raises(OvfemError):  # no adjoint of the damped recursion
-        s.adjoint(torch.zeros(s.n_rec * 3 * s.rec_nt, dtype=torch.float64, device="cuda"))
+    g_lam, g_mu = s.adjoint(torch.zeros(s.n_rec * 3 * s.rec_nt, dtype=torch.float64, device="cuda"))
+    assert not g_lam.abs().sum().item() and not g_mu.abs().sum().item()  # zero residual, zero gradient
     u = Solver.from_workload(w, precision="fp64")
     b = Batch([s, u])
     with pytest.raises(OvfemError):
         b.step(1)  # damped and undamped members
     b.close()
+
+
+def _adjoint_case(seed, nx=12, ny=10, nz=9, nt=60, zeta=0.05):
+    """Heterogeneous box, source at the surface centre, 5 surface receivers, Rayleigh
+    damping of ratio zeta across the wavelet's band; observations from a perturbed lam."""
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    rho = rng.uniform(1900, 2400, shape)
+    vs = rng.uniform(500, 1100, shape)
+    lam, mu = wl.lame_from_velocities(2.0 * vs, vs, rho)
+    h = 4.0
+    dt = wl.stable_dt(h, lam * 1.2, mu * 1.2, rho)
+    f0 = 1.0 / (18 * dt)
+    alpha, beta = oasm.rayleigh_coefficients(zeta, 0.8 * f0, 1.25 * f0)
+    src = np.array([wl.node_id(nx // 2, ny // 2, nz, nx, ny)], np.int64)
+    rec = wl.surface_nodes(rng, 5, nx, ny, nz, exclude=src)
+    w = wl.Workload("damped-adjoint", nx, ny, nz, h, lam, mu, rho, wl.box_fixed(nx, ny, nz), dt, nt, src,
+                    np.array([2], np.int32), np.array([0], np.int32), wl.ricker(nt, dt, f0)[None, :], rec)
+    mt = oasm.Model(lam * (1 + 0.1 * rng.standard_normal(shape)), mu, rho, h, w.fixed, dt, alpha=alpha, beta=beta)
+    d_obs, *_ = oasm.simulate(mt, nt, src, w.src_comp, w.wavelet, rec)
+    return w, alpha, beta, d_obs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8", "fp64-sf"])
+def test_damped_adjoint_matches_the_oracle(prec):
+    """The adjoint of the damped recursion (checkpoint segments of 9 steps) against the
+    oracle's damped adjoint, which central differences pin on the CPU."""
+    import torch
+    w, alpha, beta, d_obs = _adjoint_case(seed=45)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt, alpha=alpha, beta=beta)
+    _, gl_ref, gm_ref = oasm.adjoint_gradient(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node, d_obs)
+    m0 = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    _, gl_und, _ = oasm.adjoint_gradient(m0, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node, d_obs)
+    s = _solver(w, prec, alpha, beta)
+    s.set_checkpointing(9, w.nt)
+    s.step(w.nt)
+    res = (s.get_traces() - torch.from_numpy(d_obs).cuda()[None]).contiguous()
+    g_lam, g_mu = (g.cpu().numpy() for g in s.adjoint(res))
+    el_, em_ = _rel(g_lam, gl_ref), _rel(g_mu, gm_ref)
+    print("damped adjoint %s: %.3e %.3e (damping changes the gradient by %.2e)"
+          % (prec, el_, em_, _rel(gl_ref, gl_und)))
+    assert el_ <= TRACE_TOL and em_ <= TRACE_TOL
+    assert _rel(gl_ref, gl_und) > 1e-3
+
+
+def test_damped_autograd_and_central_differences():
+    """torch.autograd through the damped stepper; the FP64 gradient against central
+    differences of the GPU's own misfit at seeded voxels."""
+    import torch
+
+    from paper_2404_13683_amd import autograd
+    w, alpha, beta, d_obs = _adjoint_case(seed=46)
+    s = _solver(w, "int8", alpha, beta)
+    lam = torch.from_numpy(w.lam).cuda().requires_grad_(True)
+    mu = torch.from_numpy(w.mu).cuda().requires_grad_(True)
+    tr = autograd.traces(s, lam, mu, w.rho, nt=w.nt, ckpt_every=13)
+    J = 0.5 * ((tr[0] - torch.from_numpy(d_obs).cuda()) ** 2).sum()
+    J.backward()
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt, alpha=alpha, beta=beta)
+    _, gl_ref, gm_ref = oasm.adjoint_gradient(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node, d_obs)
+    assert _rel(lam.grad.cpu().numpy(), gl_ref) <= TRACE_TOL
+    assert _rel(mu.grad.cpu().numpy(), gm_ref) <= TRACE_TOL
+
+    f = _solver(w, "fp64", alpha, beta)
+
+    def J_of(la, m_):
+        f.set_model(la, m_, w.rho)
+        f.set_damping(alpha, beta)
+        f.set_dt(w.dt)
+        f.step(w.nt)
+        r = (f.get_traces() - torch.from_numpy(d_obs).cuda()).cpu().numpy()
+        return 0.5 * float(np.sum(r * r))
+
+    rng = np.random.default_rng(47)
+    g = lam.grad.cpu().numpy()
+    cand = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
+    for idx in cand[rng.choice(len(cand), size=4, replace=False)]:
+        k, j, i = map(int, idx)
+        la = w.lam.copy()
+        base = la[k, j, i]
+        eps = 1e-3 * base
+        la[k, j, i] = base + eps
+        jp = J_of(la, w.mu)
+        la[k, j, i] = base - eps
+        jm = J_of(la, w.mu)
+        fd = (jp - jm) / (2 * eps)
+        print("damped FD lam %s: adjoint %.6e fd %.6e" % ((k, j, i), g[k, j, i], fd))
+        assert abs(g[k, j, i] - fd) <= 1e-4 * abs(fd)
