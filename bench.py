@@ -92,6 +92,62 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Bytes per second (read + written) of a plain device copy of nbytes: the bandwidth an
+    HBM-bound kernel can reach on this GPU in practice."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = 2.0 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return bw
+
+
+def profile_counters(path_name):
+    """Busy fractions of the stepper kernel from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    kv = {}
+    for line in open(COUNTERS_FILE):
+        line = line.split("#", 1)[0].strip()
+        if "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    out = {}
+    for key in ("valu_busy", "mfma_busy", "waves_per_simd", "wait_frac"):
+        if "%s_%s" % (path_name, key) in kv:
+            out[key] = float(kv["%s_%s" % (path_name, key)])
+    return out or None
+
+
+def trace_errors(a, b):
+    """a against the reference b, both [..., receiver, component, step]: the pooled relative
+    L2, the largest per-channel relative L2 over channels whose norm is at least 1e-6 of the
+    largest channel's, and the error measure of Sec. 3, Eq. (18) (mean over channels of
+    sum_t (a - b)^2 / sum_t b^2, channels with a zero reference left out)."""
+    a = np.asarray(a).reshape(-1, np.shape(a)[-1])
+    b = np.asarray(b).reshape(-1, np.shape(b)[-1])
+    pooled = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    cn = np.linalg.norm(b, axis=1)
+    sel = cn >= 1e-6 * cn.max()
+    per = float(np.max(np.linalg.norm((a - b)[sel], axis=1) / cn[sel]))
+    nz = cn > 0
+    err18 = float(np.mean(np.sum((a - b)[nz] ** 2, axis=1) / cn[nz] ** 2))
+    return {"trace_rel_l2": pooled, "per_channel_max_rel_l2": per, "err_eq18": err18}
+
+
 def algorithmic_bytes(nx, ny, nz, shots=1):
     """Bytes a step must move: per shot u^n, u^{n-1} read and u^{n+1} written (72 B per node);
     once, dt^2/m per node (8 B) and lam, mu per element (16 B)."""
@@ -122,7 +178,7 @@ def time_path(wl, prec, warmup, steps, autotune=True, chunk_planes=0, stages=8, 
     if chunk_planes:
         s.set_tuning(chunk_planes=chunk_planes)
     elif autotune:
-        s.autotune(steps=10)
+        s.autotune(steps=20)
     tuning = s.get_tuning()
     s.reset()
     ms = _timed(s.step, warmup, steps)
@@ -137,7 +193,7 @@ def time_batch(wls, prec, warmup, steps):
     sols = [Solver.from_workload(w, precision=prec, receivers_nt=warmup + steps) for w in wls]
     b = Batch(sols)
     ms = _timed(b.step, warmup, steps)
-    traces = np.concatenate([s.get_traces().cpu().numpy().ravel() for s in sols])
+    traces = np.concatenate([s.get_traces().cpu().numpy().reshape(-1, warmup + steps) for s in sols])
     b.close()
     for s in sols:
         s.close()
@@ -166,9 +222,20 @@ def cpu_baseline(wl, budget_s=15.0, label=None):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    env = ", ".join("%s=%s" % (k, os.environ[k]) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")
+                    if k in os.environ)
     return {"value": wl.free_dof() * n / dt, "unit": "DOF-updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d full steps of one shot of %s (numpy FP64 oracle, %.1f s)"
-                      % (n, label or wl.name, dt)}
+            "sample": "%d full steps of one shot of %s (numpy FP64 oracle, %.1f s; %s, %d BLAS threads%s; "
+                      "%d cores visible)" % (n, label or wl.name, dt, cpu, threads, "; " + env if env else "",
+                                              len(os.sched_getaffinity(0)))}
 
 
 def make_workload(name, nt):
@@ -287,10 +354,13 @@ def main():
             out["fp64_sf_path"]["trace_rel_l2_vs_fp64"] = float(
                 np.linalg.norm(f["traces"] - res["fp64"]["traces"]) / np.linalg.norm(res["fp64"]["traces"]))
     if "fp64" in res and head != "fp64":
-        a, b = res[head]["traces"], res["fp64"]["traces"]
         out["int8_vs_fp64"] = {"speedup": res["fp64"]["ms_per_step"] / res[head]["ms_per_step"],
-                               "trace_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                               **trace_errors(res[head]["traces"], res["fp64"]["traces"]),
                                "steps_compared": nt}
+    copy_bw = copy_bandwidth()
+    out["roofline"]["copy_GBps"] = copy_bw / 1e9
+    out["roofline"]["frac_of_copy"] = hbm / copy_bw
+    out["roofline"]["counters"] = profile_counters(head) if args.workload == "c2" else None
     if args.stage_sweep and not batched and "fp64" in res:
         sweep = []
         for M in (4, 5, 6, 7):

@@ -38,6 +38,19 @@ inline void require(bool ok, const std::string& msg, ovfem_status code = OVFEM_E
   if (!ok) throw Error(code, msg);
 }
 
+// Deterministic pseudo-random values in [-scale, scale) (splitmix64 of the index): the
+// wavefield the autotuner times on, so that candidates run on data of a real run's
+// statistics rather than on the all-zero state of a fresh solver.
+__global__ void fill_random_kernel(double* v, size_t n, unsigned long long seed, double scale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = (unsigned long long)i + seed * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  v[i] = scale * ((double)(z >> 11) * 0x1p-52 - 1.0);
+}
+
 template <class F>
 ovfem_status guarded(F&& f) {
   try {
@@ -1114,6 +1127,12 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
                                s->stream));
       OVFEM_HIP(hipEventCreate(&e0));
       OVFEM_HIP(hipEventCreate(&e1));
+      // time on a filled wavefield pair (restored below)
+      const unsigned fill_blocks = (unsigned)((nv + 255) / 256);
+      fill_random_kernel<<<fill_blocks, 256, 0, s->stream>>>(s->u[s->buf_cur(s->phase)].p, nv, 1, 1e-6);
+      OVFEM_HIP(hipGetLastError());
+      fill_random_kernel<<<fill_blocks, 256, 0, s->stream>>>(s->u[s->buf_prev(s->phase)].p, nv, 2, 1e-6);
+      OVFEM_HIP(hipGetLastError());
       std::vector<int> plane_opts = {8, 12, 16, 24, 32};
       std::vector<int> persist_opts = {0};
       if (s->n_shots > 1) {
