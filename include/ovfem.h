@@ -88,10 +88,11 @@ const char* ovfem_last_error(void);
  * device, stepping n_shots (1..OVFEM_MAX_SHOTS) independent wavefields of the same
  * model at once (one per shot; every step of every shot runs in one kernel launch).
  * stream is a hipStream_t (NULL = the legacy default stream); all work is enqueued on
- * it.  precision is OVFEM_FP64, OVFEM_INT8 or OVFEM_INT8_BF16.
+ * it.  precision is OVFEM_FP64, OVFEM_INT8, OVFEM_INT8_BF16 or OVFEM_FP64_SF.
  * Device memory: 2 n_shots nodal vectors + 16 bytes per element + 8 per node.
- * EINVAL for non-positive sizes, h <= 0, unknown precision, n_shots out of range;
- * ENOMEM if the device buffers do not fit. */
+ * EINVAL for non-positive sizes, h <= 0, unknown precision, n_shots out of range,
+ * 2^31 or more nodes, or 2^32 / 24 or more nodes in one z plane (the kernels use 32-bit
+ * node ids and in-plane byte offsets); ENOMEM if the device buffers do not fit. */
 ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz, double h,
                           int32_t n_shots, int32_t precision, void* stream);
 

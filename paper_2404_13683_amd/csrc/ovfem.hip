@@ -684,6 +684,10 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
     require(valid_precision(precision), "ovfem_create: unknown precision");
     const double nn = double(nx + 1) * double(ny + 1) * double(nz + 1);
     require(nn < 2147483647.0, "ovfem_create: more than 2^31 - 1 nodes");
+    // the kernels address a node plane ([node][3] doubles) and an element layer ([element][2]
+    // doubles) with 32-bit byte offsets
+    require(24.0 * double(nx + 1) * double(ny + 1) < 4294967296.0,
+            "ovfem_create: more than 2^32 / 24 nodes in one z plane");
     auto s = new ovfem_solver();
     try {
       OVFEM_HIP(hipGetDevice(&s->device));

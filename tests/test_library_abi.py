@@ -48,6 +48,11 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 0, 0, None) == -1
     assert lib.ovfem_create(ctypes.byref(h), 4, 4, 4, 1.0, 4097, 0, None) == -1
     assert b"n_shots" in lib.ovfem_last_error()
+    # grids beyond the index ranges of the kernels
+    assert lib.ovfem_create(ctypes.byref(h), 2048, 2048, 1024, 1.0, 1, 0, None) == -1
+    assert b"2^31" in lib.ovfem_last_error()
+    assert lib.ovfem_create(ctypes.byref(h), 14000, 14000, 4, 1.0, 1, 0, None) == -1
+    assert b"z plane" in lib.ovfem_last_error()
     assert lib.ovfem_step(None, 1) == -1
     assert lib.ovfem_set_tuning(None, 16, 0, 64) == -1
     assert lib.ovfem_autotune(None, 10, None) == -1
