@@ -80,7 +80,7 @@ static_assert((long long)kMaxRowAbs * 128 * 257 < 2147483647LL, "digit-pair sums
 enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
 // PATH_INT8: digits on i8 matrix cores, INT32 accumulation with a shift per pair;
 // PATH_BF16: digit pairs on bf16 matrix cores, exact FP32 accumulation.
-// PATH_FP64SF: the OVFEM element product in FP64, sum-factorised (element_sf).
+// PATH_FP64SF: the OVFEM element product in FP64, sum-factorised (sf_transform, sf_component).
 enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_BF16 = 2, PATH_FP64SF = 3 };
 constexpr bool is_f64_path(int p) { return p == PATH_FP64 || p == PATH_FP64SF; }
 
@@ -304,9 +304,11 @@ __device__ inline void element_fp64(const double ue[24], double lam_s, double mu
 //     s_b(c, j) = lam_h tr_b delta_cj + mu_h (W_c[b + {j}] + W_j[b + {c}]),
 //     tr_b = sum_{i not in b} W_i[b + {i}].
 // Both transforms are 3-level butterflies: about 250 flops per element instead of the
-// 2304 of the dense product.
-__device__ inline void element_sf(const double ue[24], double lam_h, double mu_h, double y[24]) {
-  double W[3][8];
+// 2304 of the dense product.  The kernel forms W and tr once (sf_transform), then each
+// output component in turn (sf_component), so that only one component's V is live.
+constexpr int kSfB[7] = {0, 1, 2, 4, 3, 6, 5};  // the seven stress monomials b as axis masks
+
+__device__ inline void sf_transform(const double ue[24], double W[3][8], double tr[7]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
 #pragma unroll
@@ -321,51 +323,51 @@ __device__ inline void element_sf(const double ue[24], double lam_h, double mu_h
           W[i][a | (1 << k)] = hi - lo;  // k in S: rbar_k = +1 at bit 1, -1 at bit 0
         }
   }
-  double V[3][8];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int a = 0; a < 8; ++a) V[i][a] = 0.0;
-  const double f0 = 1.0 / 16.0, f1 = f0 * 0.75, f2 = f1 * 0.75;
-  const double lb[3] = {lam_h * f0, lam_h * f1, lam_h * f2}, mb[3] = {mu_h * f0, mu_h * f1, mu_h * f2};
-  // the seven stress monomials: b = {}, {0}, {1}, {2}, {0,1}, {1,2}, {0,2}
-  constexpr int kB[7] = {0, 1, 2, 4, 3, 6, 5};
 #pragma unroll
   for (int ib = 0; ib < 7; ++ib) {
-    const int b = kB[ib];
-    const int nb = (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1);
-    double tr = 0.0;
+    const int b = kSfB[ib];
+    double t = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      if (!((b >> i) & 1)) tr += W[i][b | (1 << i)];
+      if (!((b >> i) & 1)) t += W[i][b | (1 << i)];
+    tr[ib] = t;
+  }
+}
+
+// Component c of y: y[alpha] = y_{alpha,c}, alpha = 0..7.
+__device__ inline void sf_component(const double W[3][8], const double tr[7], double lam_h, double mu_h, int c,
+                                    double y[8]) {
+  double V[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) V[a] = 0.0;
+  const double f0 = 1.0 / 16.0, f1 = f0 * 0.75, f2 = f1 * 0.75;
+  const double lb[3] = {lam_h * f0, lam_h * f1, lam_h * f2}, mb[3] = {mu_h * f0, mu_h * f1, mu_h * f2};
+#pragma unroll
+  for (int ib = 0; ib < 7; ++ib) {
+    const int b = kSfB[ib];
+    const int nb = (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if ((b >> j) & 1) continue;
       const int S = b | (1 << j);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double g = W[c][S];                            // (psi^b, d_j u_c) up to the factor
-        if (!((b >> c) & 1)) g += W[j][b | (1 << c)];  // + (psi^b, d_c u_j)
-        double sig = mb[nb] * g;
-        if (c == j) sig = fma(lb[nb], tr, sig);
-        V[c][S] += sig;
-      }
+      double g = W[c][S];                            // (psi^b, d_j u_c) up to the factor
+      if (!((b >> c) & 1)) g += W[j][b | (1 << c)];  // + (psi^b, d_c u_j)
+      double sig = mb[nb] * g;
+      if (c == j) sig = fma(lb[nb], tr[ib], sig);
+      V[S] += sig;
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+  for (int k = 2; k >= 0; --k)
 #pragma unroll
-    for (int k = 2; k >= 0; --k)
+    for (int a = 0; a < 8; ++a)
+      if (!((a >> k) & 1)) {
+        const double v0 = V[a], v1 = V[a | (1 << k)];
+        V[a] = v0 - v1;            // rbar_k = -1
+        V[a | (1 << k)] = v0 + v1;  // rbar_k = +1
+      }
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (!((a >> k) & 1)) {
-          const double v0 = V[c][a], v1 = V[c][a | (1 << k)];
-          V[c][a] = v0 - v1;            // rbar_k = -1
-          V[c][a | (1 << k)] = v0 + v1;  // rbar_k = +1
-        }
-#pragma unroll
-    for (int a = 0; a < 8; ++a) y[3 * a + c] = V[c][a];
-  }
+  for (int a = 0; a < 8; ++a) y[a] = V[a];
 }
 
 // v of the lane one to the left within its row of 16 lanes (0 for the first lane).
@@ -579,6 +581,8 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 
     // ---- element layer k -> in-plane sums for plane k
     if (F64) {
+      // bottom-corner contributions (with the previous layer's top ones) go to the in-plane
+      // sums of plane k; top-corner contributions are kept for plane k + 1
       double y[24];
       if (layer_ok) {
         const double* Pb = ringf + bot * FPLANE;
@@ -591,23 +595,39 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 #pragma unroll
           for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PN + tb + dj) * PN + ta + di];
         }
-        if constexpr (PATH == PATH_FP64SF)
-          element_sf(ue, mat_e.x * 256.0, mat_e.y * 128.0, y);  // mat holds h lam / 256, h mu / 128
-        else
+        if constexpr (PATH == PATH_FP64SF) {
+          // one output component at a time (fewer live registers)
+          double W[3][8], tr[7];
+          sf_transform(ue, W, tr);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double yc[8];
+            sf_component(W, tr, mat_e.x * 256.0, mat_e.y * 128.0, c, yc);  // mat holds h lam / 256, h mu / 128
+            const double v0 = yc[0] + top_f[c], v1 = yc[1] + top_f[3 + c];
+            const double v2 = yc[2] + top_f[6 + c], v3 = yc[3] + top_f[9 + c];
+            lsum[(tb * 3 + c) * TE + ta] = v0 + row_shift_right(v1);  // node (ta, tb)
+            usum[(tb * 3 + c) * TE + ta] = v2 + row_shift_right(v3);  // node (ta, tb + 1)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) top_f[3 * a + c] = yc[4 + a];
+          }
+        } else {
           element_fp64<ELEM>(ue, mat_e.x, mat_e.y, y);
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < 24; ++i) y[i] = 0.0;
       }
+      if (PATH != PATH_FP64SF || !layer_ok) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double v0 = y[c] + top_f[c], v1 = y[3 + c] + top_f[3 + c];
-        const double v2 = y[6 + c] + top_f[6 + c], v3 = y[9 + c] + top_f[9 + c];
-        lsum[(tb * 3 + c) * TE + ta] = v0 + row_shift_right(v1);  // node (ta, tb)
-        usum[(tb * 3 + c) * TE + ta] = v2 + row_shift_right(v3);  // node (ta, tb + 1)
+        for (int c = 0; c < 3; ++c) {
+          const double v0 = y[c] + top_f[c], v1 = y[3 + c] + top_f[3 + c];
+          const double v2 = y[6 + c] + top_f[6 + c], v3 = y[9 + c] + top_f[9 + c];
+          lsum[(tb * 3 + c) * TE + ta] = v0 + row_shift_right(v1);  // node (ta, tb)
+          usum[(tb * 3 + c) * TE + ta] = v2 + row_shift_right(v3);  // node (ta, tb + 1)
+        }
+#pragma unroll
+        for (int i = 0; i < 12; ++i) top_f[i] = y[12 + i];
       }
-#pragma unroll
-      for (int i = 0; i < 12; ++i) top_f[i] = y[12 + i];
     } else {
       const int ja = lane & 15, G = lane >> 4;  // element column; lane group
       const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_BF16 ? DPLANE : St::PLANE);
