@@ -130,6 +130,12 @@ class Solver:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     # --- configuration (host arrays)
     def set_precision(self, precision):
         _check(_LIB.ovfem_set_precision(self._h, PRECISIONS[precision]))
@@ -310,3 +316,9 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
