@@ -1,0 +1,153 @@
+"""GPU: degenerate inputs of the stepper, against the oracle.
+
+Free vibration with no sources (and the conservation of the discrete energy of Sec. 2,
+Eq. (3) along the GPU's own states), no receivers, sources on fixed nodes, repeated
+sources on one degree of freedom, a wavelet and a receiver window shorter than the run,
+and a model made mostly of removed voxels.  Every path; traces and wavefields to the
+same 1e-9 bar as the other runs.
+"""
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from paper_2404_13683_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "int8", "fp64-sf"]
+TOL = 1e-9
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _case(seed, nt=120):
+    return wl.layered_c2(nx=20, ny=18, nz=14, f0=40.0, nt=nt, seed=seed)
+
+
+def _model(w, solid=None):
+    return oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt, solid=solid)
+
+
+def _solver(w, prec, solid=None):
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver(w.nx, w.ny, w.nz, w.h, precision=prec)
+    s.set_model(w.lam, w.mu, w.rho, solid)
+    s.set_fixed_nodes(w.fixed)
+    s.set_dt(w.dt)
+    return s
+
+
+def _smooth_field(w, seed):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(w.nz + 1), np.arange(w.ny + 1), np.arange(w.nx + 1), indexing="ij")
+    u = np.empty((w.nz + 1, w.ny + 1, w.nx + 1, 3))
+    for c in range(3):
+        k = rng.uniform(0.2, 0.6, 3)
+        u[..., c] = np.sin(k[0] * x + k[1] * y + k[2] * z + c)
+    return u * 1e-6
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).cuda()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_free_vibration_without_sources(prec):
+    w = _case(61)
+    m = _model(w)
+    u0 = _smooth_field(w, 62)
+    up0 = u0 * 0.999
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, [], [], np.zeros((0, w.nt)), w.rec_node, u0=u0, u_prev=up0)
+    s = _solver(w, prec)
+    s.set_sources(np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros((0, 1)))
+    s.set_receivers(w.rec_node, w.nt)
+    s.set_wavefield(_cuda(u0), _cuda(up0), step=0)
+    energies = []
+    for _ in range(4):
+        s.step(w.nt // 4)
+        un = s.get_wavefield(0).cpu().numpy().reshape(u0.shape)
+        unm1 = s.get_wavefield(1).cpu().numpy().reshape(u0.shape)
+        energies.append(oasm.energy(m, un, unm1))
+    et = _rel(s.get_traces().cpu().numpy()[0], ref)
+    eu = _rel(un, u_ref)
+    drift = max(abs(e - energies[0]) for e in energies) / abs(energies[0])
+    print("free vibration %s: traces %.3e wavefield %.3e energy drift %.3e" % (prec, et, eu, drift))
+    assert et <= TOL and eu <= TOL
+    assert drift <= 1e-10
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_no_receivers(prec):
+    w = _case(63, nt=40)
+    m = _model(w)
+    _, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, np.zeros(0, np.int64))
+    s = _solver(w, prec)
+    s.set_sources(w.src_node, w.src_comp, w.wavelet)
+    s.set_receivers(np.zeros(0, np.int64), 0)
+    s.step(w.nt)
+    assert tuple(s.get_traces().shape) == (1, 0, 3, 0)
+    assert _rel(s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape), u_ref) <= TOL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fixed_node_repeated_and_short_sources(prec):
+    """A force on a fixed node does nothing; two forces on one degree of freedom add; the
+    wavelet table covers half the run (no force afterwards); receivers record the first
+    third of the run only."""
+    w = _case(64)
+    nt = w.nt
+    centre = int(w.src_node[0])
+    fixed_node = wl.node_id(0, w.ny // 2, w.nz // 2, w.nx, w.ny)  # on the x = 0 face
+    assert w.fixed[fixed_node // ((w.nx + 1) * (w.ny + 1)),
+                   (fixed_node // (w.nx + 1)) % (w.ny + 1), fixed_node % (w.nx + 1)]
+    nodes = np.array([centre, centre, fixed_node, centre], np.int64)
+    comps = np.array([2, 2, 0, 0], np.int32)
+    rk = wl.ricker(nt // 2, w.dt, 40.0)
+    wav = np.stack([rk, 0.5 * rk, rk, -0.25 * rk])
+    rec_nt = nt // 3
+    full = np.zeros((len(nodes), nt))
+    full[:, :nt // 2] = wav
+    m = _model(w)
+    ref, _, _, _ = oasm.simulate(m, nt, nodes, comps, full, w.rec_node)
+    s = _solver(w, prec)
+    s.set_sources(nodes, comps, wav)
+    s.set_receivers(w.rec_node, rec_nt)
+    s.step(nt)
+    tr = s.get_traces().cpu().numpy()[0]
+    assert tr.shape[-1] == rec_nt
+    err = _rel(tr, ref[..., :rec_nt])
+    u = s.get_wavefield(0).cpu().numpy().reshape(-1, 3)
+    print("fixed/repeated/short sources %s: traces %.3e" % (prec, err))
+    assert err <= TOL
+    assert np.all(u[fixed_node] == 0.0)
+    # the source terms really are summed: dropping the second one changes the traces
+    ref2, _, _, _ = oasm.simulate(m, nt, nodes[[0, 2, 3]], comps[[0, 2, 3]], full[[0, 2, 3]], w.rec_node)
+    assert _rel(ref2[..., :rec_nt], ref[..., :rec_nt]) > 1e-2
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mostly_removed_voxels(prec):
+    """A model with 60 % of its voxels removed (seeded): nodes touching no solid voxel keep
+    zero mass and never move."""
+    w = _case(65)
+    rng = np.random.default_rng(66)
+    solid = (rng.random((w.nz, w.ny, w.nx)) < 0.4).astype(np.uint8)
+    solid[:, w.ny // 2 - 2:w.ny // 2 + 2, w.nx // 2 - 2:w.nx // 2 + 2] = 1  # the source column
+    m = _model(w, solid)
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    s = _solver(w, prec, solid)
+    s.set_sources(w.src_node, w.src_comp, w.wavelet)
+    s.set_receivers(w.rec_node, w.nt)
+    s.step(w.nt)
+    u = s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape)
+    eu = _rel(u, u_ref)
+    print("mostly removed voxels %s: wavefield %.3e" % (prec, eu))
+    assert eu <= TOL
+    massless = oasm.nodal_mass(w.rho, w.h, solid.astype(bool)) == 0
+    assert massless.any() and np.all(u[massless] == 0.0)
+    tr = s.get_traces().cpu().numpy()[0]
+    if np.linalg.norm(ref) > 0:
+        assert _rel(tr, ref) <= TOL
