@@ -282,8 +282,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); the multi-GPU "
-              "sharding is described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
+        print("bench.py: the stepper runs on one GPU (--gpus %d requested); it does not shard a "
+              "model or its shots across GPUs" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     if args.steps is None:
