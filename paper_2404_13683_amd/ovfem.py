@@ -199,6 +199,21 @@ class Solver:
         return s
 
     # --- stepping and data (device tensors)
+    # The library runs everything on the solver's stream.  Device tensors the caller made
+    # on another stream are ordered before the library's work on them, and the library's
+    # outputs before the caller's stream goes on.
+    def _order_in(self):
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _order_out(self):
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def reset(self):
         _check(_LIB.ovfem_reset(self._h))
 
@@ -213,7 +228,9 @@ class Solver:
         n = 3 * self.n_nodes
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=u.device)
+        self._order_in()
         _check(_LIB.ovfem_matvec(self._h, _dev_f64(u, n, "u"), _dev_f64(out, n, "out")))
+        self._order_out()
         return out
 
     def get_wavefield(self, which=0, out=None):
@@ -222,19 +239,24 @@ class Solver:
         n = self.n_shots * 3 * self.n_nodes
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device="cuda")
+        self._order_in()
         _check(_LIB.ovfem_get_wavefield(self._h, int(which), _dev_f64(out, n, "out")))
+        self._order_out()
         return out
 
     def set_wavefield(self, un, unm1, step=0):
         n = self.n_shots * 3 * self.n_nodes
+        self._order_in()
         _check(_LIB.ovfem_set_wavefield(self._h, _dev_f64(un, n, "un"), _dev_f64(unm1, n, "unm1"), int(step)))
 
     def get_traces(self, out=None):
         import torch
         n = self.n_shots * self.n_rec * 3 * self.rec_nt
         if out is None:
-            out = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")[:n]
+            out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")[:n]
+        self._order_in()
         _check(_LIB.ovfem_get_traces(self._h, _dev_f64(out, n, "out") if n else None))
+        self._order_out()
         return out.view(self.n_shots, self.n_rec, 3, self.rec_nt)
 
     def set_checkpointing(self, every, max_steps):
@@ -248,8 +270,10 @@ class Solver:
         ne = self.nx * self.ny * self.nz
         g_lam = torch.empty(ne, dtype=torch.float64, device="cuda")
         g_mu = torch.empty(ne, dtype=torch.float64, device="cuda")
+        self._order_in()
         _check(_LIB.ovfem_adjoint(self._h, _dev_f64(r, n, "residual"), _dev_f64(g_lam, ne, "g_lam"),
                                   _dev_f64(g_mu, ne, "g_mu")))
+        self._order_out()
         shape = (self.nz, self.ny, self.nx)
         return g_lam.view(shape), g_mu.view(shape)
 
