@@ -17,6 +17,7 @@ Other workloads (parity cases, one JSON line each, not the headline):
   --workload c3-shots    64 shots on 128 x 128 x 64 in one launch per step
   --workload c3-uneven   16 layered domains of uneven size, one batched launch per step
   --workload c5          512 x 512 x 256 fractal topography over a basin, air removed
+  --workload c5-slab     512 x 512 x 32 of the same recipe: one GPU's share of c5 split 8 ways
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload NAME]
 (--steps defaults to the workload's run length: 2000 for c2, 1000 for c3, 4000 for c5)
@@ -44,7 +45,7 @@ FP64_FLOP_PER_ELEMENT = 2 * 2 * 24 * 24   # AL u and AM u in FP64
 # run length of each workload: the trace comparison between the paths covers the whole run
 # (in the first few hundred steps of the large models the receivers see only the scheme's
 # numerical precursor, amplitudes far below any arrival, where relative errors mean little)
-FULL_STEPS = {"c2": 2000, "c3-shots": 1000, "c3-uneven": 1000, "c5": 4000}
+FULL_STEPS = {"c2": 2000, "c3-shots": 1000, "c3-uneven": 1000, "c5": 4000, "c5-slab": 4000}
 
 KERNEL_SOURCES = ["paper_2404_13683_amd/csrc/kernels.hpp", "paper_2404_13683_amd/csrc/refmat.hpp"]
 EQUAL_ACCURACY = os.path.join(ROOT, "tests", "golden", "equal_dispersion_accuracy.json")
@@ -257,6 +258,11 @@ def make_workload(name, nt):
         w = workloads.topography_c5(nt=nt)
         return [w], ("topography-basin-512x512x256 (67M voxels, %d free DOF, air removed), h=2 m, dt=%.4e s"
                      % (w.free_dof(), w.dt)), False
+    if name == "c5-slab":
+        # one GPU's share of the 512 x 512 x 256 model split eight ways along z
+        w = workloads.topography_c5(nz=32, nt=nt)
+        return [w], ("topography-basin slab 512x512x32 (one eighth of the 512x512x256 model along z, "
+                     "%d free DOF), h=2 m, dt=%.4e s" % (w.free_dof(), w.dt)), False
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -270,7 +276,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--paths", default="fp64,int8,fp64-sf")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3-shots", "c3-uneven", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3-shots", "c3-uneven", "c5", "c5-slab"])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--chunk-planes", type=int, default=0, help="fixed z-chunk depth instead of autotuning")
     ap.add_argument("--no-equal-accuracy", action="store_true", help="skip the trilinear comparison")
