@@ -102,3 +102,44 @@ def test_modal_decay_converges_to_the_continuum_rate(kind):
         # backward stiffness term: first order, error close to the stiffness share of zeta w dt
         assert errs[1] < 2e-3
         assert 1.7 < errs[0] / errs[1] < 2.3
+
+
+def _highest_mode(lam, mu, rho, h, fixed):
+    """Highest generalized eigenpair (w^2, phi) of K phi = w^2 M phi on the free DOFs."""
+    m0 = oasm.Model(lam, mu, rho, h, fixed, 1.0)
+    K = oasm.dense_stiffness(lam, mu, h)
+    free = np.repeat(m0.free.reshape(-1), 3)
+    mass = np.repeat(m0.mass.reshape(-1), 3)[free]
+    s = 1.0 / np.sqrt(mass)
+    w2, V = np.linalg.eigh(s[:, None] * K[np.ix_(free, free)] * s[None, :])
+    phi = np.zeros(free.size)
+    phi[free] = s * V[:, -1]
+    return w2[-1], phi.reshape(m0.node_shape)
+
+
+@pytest.mark.parametrize("side", [0.98, 1.02])
+def test_damped_stability_bound(side):
+    """The damped step is stable exactly while w_max^2 dt (dt + 2 beta) <= 4 (the
+    Jury conditions of the modal recurrence; independent of alpha >= 0): started on the
+    highest mode, 2 % below that dt the mode stays bounded, 2 % above it grows."""
+    lam, mu, rho, h, fixed = _box()
+    w2, phi = _highest_mode(lam, mu, rho, h, fixed)
+    w = np.sqrt(w2)
+    beta = 0.3 / w
+    alpha = 0.02 * w
+    dt = side * (-beta + np.sqrt(beta * beta + 4.0 / w2))
+    m = oasm.Model(lam, mu, rho, h, fixed, dt, alpha=alpha, beta=beta)
+    Mphi = m.mass[..., None] * phi
+    norm = float(np.sum(Mphi * phi))
+    u, up = phi.copy(), phi.copy()
+    zero = np.zeros(m.node_shape)
+    amp = []
+    for _ in range(3000):
+        un = m.step(u, up, zero)
+        up, u = u, un
+        amp.append(abs(float(np.sum(Mphi * u)) / norm))
+    print("side %.2f: |a| after 100, 1000, 3000 steps: %.3e %.3e %.3e" % (side, amp[99], amp[999], amp[-1]))
+    if side < 1.0:
+        assert max(amp) < 2.0
+    else:
+        assert amp[-1] > 1e3 and amp[-1] > 100 * amp[999]
