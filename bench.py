@@ -388,15 +388,22 @@ def main():
         # numerical dispersion (oracle Bloch analysis, stored with the script that wrote it)
         ms_t, _, tun_t = time_path(wls[0], "fp64", args.warmup, args.steps, autotune=not args.no_autotune,
                                    chunk_planes=args.chunk_planes, element="trilinear")
+        ms_ts, _, _ = time_path(wls[0], "fp64-sf", args.warmup, args.steps, autotune=not args.no_autotune,
+                                chunk_planes=args.chunk_planes, element="trilinear")
         fx = json.load(open(EQUAL_ACCURACY))
         row = [r for r in fx["rows"] if r["ppw_ovfem"] == 10][0]
         out["equal_accuracy"] = {
             "trilinear_fp64_ms_per_step": ms_t, "trilinear_tuning": tun_t,
+            "trilinear_fp64_sf_ms_per_step": ms_ts,
             "dispersion_h_ratio": row["h_ratio"], "refinement_cost_factor": row["cost_factor"],
             "at": "10 points per S wavelength, RMS phase error %.2e" % row["rms_phase_error"],
             "speedup_vs_trilinear_fp64": row["cost_factor"] * ms_t / res["int8"]["ms_per_step"],
+            "speedup_vs_trilinear_fp64_sf": row["cost_factor"] * ms_ts / res["int8"]["ms_per_step"],
+            "sf_ovfem_vs_sf_trilinear": (row["cost_factor"] * ms_ts / res["fp64-sf"]["ms_per_step"]
+                                         if "fp64-sf" in res else None),
             "context": "the paper reports 17.0x for INT8 OVFEM vs FP64 VFEM on an A100 (its own waveform error measure)"}
-        print("[bench] trilinear fp64: %.4f ms/step" % ms_t, file=sys.stderr, flush=True)
+        print("[bench] trilinear fp64: %.4f ms/step, fp64-sf: %.4f ms/step" % (ms_t, ms_ts), file=sys.stderr,
+              flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_budget, label=desc)
     print(json.dumps(out))

@@ -26,6 +26,8 @@
  *     of Eq. (5) a scaled Walsh coefficient of the 8 corner values, so K_e u_e is two
  *     8-point butterflies around a small stress evaluation (~250 instead of 2304 flops
  *     per element).  A stronger FP64 baseline than the dense "as is" form of Sec. 3.
+ *     The trilinear element (ovfem_set_element) has the same factorisation with other
+ *     weights of the strain moments, so OVFEM_FP64_SF runs it as well.
  *
  * Grid layout (shared by every array argument):
  *   elements e = i + nx (j + ny k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz;
@@ -68,7 +70,7 @@ typedef int32_t ovfem_status;
 #define OVFEM_FP64 0
 #define OVFEM_INT8 1      /* INT8 digit slices, int8 matrix cores, INT32 accumulation */
 #define OVFEM_INT8_BF16 2 /* INT8 digit slices, bf16 matrix cores, exact FP32 digit-pair sums */
-#define OVFEM_FP64_SF 3   /* FP64, the OVFEM element product sum-factorised (OVFEM element only) */
+#define OVFEM_FP64_SF 3   /* FP64, the element product sum-factorised */
 
 /* limits */
 #define OVFEM_MAX_SHOTS 4096 /* shots per solver */
@@ -101,7 +103,7 @@ ovfem_status ovfem_destroy(ovfem_solver* s);
 
 /* Switch the precision of the element products (OVFEM_FP64 / OVFEM_INT8 / OVFEM_INT8_BF16 /
  * OVFEM_FP64_SF).  EINVAL for OVFEM_INT8_BF16 while the stage count (ovfem_set_stages)
- * is not 8, and for OVFEM_FP64_SF with the trilinear element. */
+ * is not 8. */
 ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision);
 
 /* Per-element material, HOST arrays of nx*ny*nz float64: Lame lam, shear modulus mu,
@@ -200,7 +202,8 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
  * integrated exactly by 2x2x2 Gauss points; the same lumped mass rho h^3 / 8 per node
  * and element).  Its matrices scaled by 72 are integer matrices in -32..32, so every
  * precision runs it (FP64 with the matrices as constants, the INT8 forms with them as
- * A operands, material scaled by h lam / 72, h mu / 72).  Clears the model and dt (set
+ * A operands, material scaled by h lam / 72, h mu / 72; OVFEM_FP64_SF in its
+ * sum-factorised form).  Clears the model and dt (set
  * them again) and resets the wavefield.  EINVAL for an unknown element. */
 ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element);
 

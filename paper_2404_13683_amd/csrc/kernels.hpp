@@ -306,6 +306,12 @@ __device__ inline void element_fp64(const double ue[24], double lam_s, double mu
 // Both transforms are 3-level butterflies: about 250 flops per element instead of the
 // 2304 of the dense product.  The kernel forms W and tr once (sf_transform), then each
 // output component in turn (sf_component), so that only one component's V is live.
+// The lumped trilinear element (2 x 2 x 2 Gauss points, which integrate its stiffness
+// exactly) has the same form: its displacement is the multilinear polynomial
+// (1/8) sum_S W[S] r^S, the monomials are orthogonal with (r^T, r^T) = 8 3^-|T| on the
+// reference cube, and the energy of the strain moments gives the weights
+// (1/16)(1/3)^|b| in place of OVFEM's (1/16)(3/4)^|b| (ELEM = 1): the two elements differ
+// only in how strongly the strain moments that vary across the element are weighted.
 constexpr int kSfB[7] = {0, 1, 2, 4, 3, 6, 5};  // the seven stress monomials b as axis masks
 
 __device__ inline void sf_transform(const double ue[24], double W[3][8], double tr[7]) {
@@ -334,13 +340,15 @@ __device__ inline void sf_transform(const double ue[24], double W[3][8], double 
   }
 }
 
-// Component c of y: y[alpha] = y_{alpha,c}, alpha = 0..7.
+// Component c of y: y[alpha] = y_{alpha,c}, alpha = 0..7.  ELEM: 0 OVFEM, 1 trilinear.
+template <int ELEM>
 __device__ inline void sf_component(const double W[3][8], const double tr[7], double lam_h, double mu_h, int c,
                                     double y[8]) {
   double V[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) V[a] = 0.0;
-  const double f0 = 1.0 / 16.0, f1 = f0 * 0.75, f2 = f1 * 0.75;
+  constexpr double q = ELEM == 1 ? 1.0 / 3.0 : 0.75;  // weight ratio per axis of a strain moment
+  const double f0 = 1.0 / 16.0, f1 = f0 * q, f2 = f1 * q;
   const double lb[3] = {lam_h * f0, lam_h * f1, lam_h * f2}, mb[3] = {mu_h * f0, mu_h * f1, mu_h * f2};
 #pragma unroll
   for (int ib = 0; ib < 7; ++ib) {
@@ -602,7 +610,8 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             double yc[8];
-            sf_component(W, tr, mat_e.x * 256.0, mat_e.y * 128.0, c, yc);  // mat holds h lam / 256, h mu / 128
+            // mat holds h lam / kElemScaleLam, h mu / kElemScaleMu
+            sf_component<ELEM>(W, tr, mat_e.x * kElemScaleLam[ELEM], mat_e.y * kElemScaleMu[ELEM], c, yc);
             const double v0 = yc[0] + top_f[c], v1 = yc[1] + top_f[3 + c];
             const double v2 = yc[2] + top_f[6 + c], v3 = yc[3] + top_f[9 + c];
             lsum[(tb * 3 + c) * TE + ta] = v0 + row_shift_right(v1);  // node (ta, tb)

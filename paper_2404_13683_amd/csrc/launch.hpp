@@ -28,6 +28,7 @@ void launch_list(bool damp, int grid, const KArgs* units, const int* begin, int 
 OVFEM_DECLARE_LAUNCHERS(PATH_FP64, 8, 0)
 OVFEM_DECLARE_LAUNCHERS(PATH_FP64, 8, 1)
 OVFEM_DECLARE_LAUNCHERS(PATH_FP64SF, 8, 0)
+OVFEM_DECLARE_LAUNCHERS(PATH_FP64SF, 8, 1)
 OVFEM_DECLARE_LAUNCHERS(PATH_BF16, 8, 0)
 OVFEM_DECLARE_LAUNCHERS(PATH_INT8, 4, 0)
 OVFEM_DECLARE_LAUNCHERS(PATH_INT8, 5, 0)

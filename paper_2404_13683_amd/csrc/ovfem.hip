@@ -196,7 +196,10 @@ void launch_unit(Form f, const KArgs& A, const long long* base, long long step, 
       default: launch_tiles<PATH_INT8, 8, 0>(MODE, d, A, base, step, stream); break;
     }
   } else if (f.precision == OVFEM_FP64_SF) {
-    launch_tiles<PATH_FP64SF, 8, 0>(MODE, d, A, base, step, stream);
+    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
+      launch_tiles<PATH_FP64SF, 8, 1>(MODE, d, A, base, step, stream);
+    else
+      launch_tiles<PATH_FP64SF, 8, 0>(MODE, d, A, base, step, stream);
   } else {
     launch_tiles<PATH_BF16, 8, 0>(MODE, d, A, base, step, stream);
   }
@@ -224,7 +227,10 @@ void launch_units(Form f, const KArgs* units, const int* begin, int n_units, int
       default: launch_list<PATH_INT8, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
     }
   } else if (f.precision == OVFEM_FP64_SF) {
-    launch_list<PATH_FP64SF, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+    if (f.elem == OVFEM_ELEMENT_TRILINEAR)
+      launch_list<PATH_FP64SF, 8, 1>(d, grid, units, begin, n_units, total, base, step, stream);
+    else
+      launch_list<PATH_FP64SF, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
   } else {
     launch_list<PATH_BF16, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
   }
@@ -738,8 +744,6 @@ ovfem_status ovfem_set_precision(ovfem_solver* s, int32_t precision) {
     require(valid_precision(precision), "ovfem_set_precision: unknown precision");
     require(precision != OVFEM_INT8_BF16 || s->stages == 8,
             "ovfem_set_precision: OVFEM_INT8_BF16 runs 8 digit stages only (call ovfem_set_stages(s, 8) first)");
-    require(precision != OVFEM_FP64_SF || s->element == OVFEM_ELEMENT_OVFEM,
-            "ovfem_set_precision: OVFEM_FP64_SF is the OVFEM element's factorisation");
     s->precision = precision;
   });
 }
@@ -995,8 +999,6 @@ ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_element: solver is NULL");
     require(element == OVFEM_ELEMENT_OVFEM || element == OVFEM_ELEMENT_TRILINEAR, "ovfem_set_element: unknown element");
-    require(element == OVFEM_ELEMENT_OVFEM || s->precision != OVFEM_FP64_SF,
-            "ovfem_set_element: OVFEM_FP64_SF is the OVFEM element's factorisation");
     s->check_device();
     if (element == s->element) return;
     DevBuf<uint32_t> bf;

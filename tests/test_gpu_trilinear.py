@@ -9,7 +9,7 @@ from paper_2404_13683_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp64", "int8", "int8-bf16"]
+PRECS = ["fp64", "int8", "int8-bf16", "fp64-sf"]
 
 
 def _rel(a, b):
@@ -49,7 +49,7 @@ def test_trilinear_traces(prec):
     assert et <= 1e-9 and eu <= 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp64", "int8"])
+@pytest.mark.parametrize("prec", ["fp64", "int8", "fp64-sf"])
 def test_trilinear_adjoint_matches_the_oracle(prec):
     import torch
     nx, ny, nz, nt = 12, 10, 9, 50
