@@ -80,7 +80,7 @@ static_assert((long long)kMaxRowAbs * 128 * 257 < 2147483647LL, "digit-pair sums
 enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
 // PATH_INT8: digits on i8 matrix cores, INT32 accumulation with a shift per pair;
 // PATH_BF16: digit pairs on bf16 matrix cores, exact FP32 accumulation.
-// PATH_FP64SF: the OVFEM element product in FP64, sum-factorised (sf_transform, sf_component).
+// PATH_FP64SF: the element product in FP64, sum-factorised (sf_transform, sf_component).
 enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_BF16 = 2, PATH_FP64SF = 3 };
 constexpr bool is_f64_path(int p) { return p == PATH_FP64 || p == PATH_FP64SF; }
 
