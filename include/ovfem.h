@@ -279,6 +279,13 @@ ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups);
  * (ESTATE otherwise).  Invalidates the members' checkpointed forward runs. */
 ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n);
 
+/* Blow-up check: *finite = 1 if every value of the current wavefield pair (u^n, u^{n-1})
+ * of every shot is finite, 0 if any is NaN or infinite.  With dt inside the bound that
+ * ovfem_set_dt enforces the scheme is stable, so non-finite values come from non-finite
+ * inputs (wavefields passed to ovfem_set_wavefield, source wavelets).  finite is HOST
+ * memory.  Waits for the stream.  EINVAL for NULL arguments. */
+ovfem_status ovfem_check_finite(ovfem_solver* s, int32_t* finite);
+
 /* Wait for all work enqueued by the solver. */
 ovfem_status ovfem_synchronize(ovfem_solver* s);
 

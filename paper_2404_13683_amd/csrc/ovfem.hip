@@ -38,6 +38,21 @@ inline void require(bool ok, const std::string& msg, ovfem_status code = OVFEM_E
   if (!ok) throw Error(code, msg);
 }
 
+// Per block: 1 if any of its values of v is not finite (NaN or infinite), else 0.  One
+// plain store per block; the host ORs the block flags.
+constexpr int kFiniteBlocks = 1024;
+__global__ void nonfinite_kernel(const double* v, size_t n, int* flags) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  int bad = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(v[i]);
+  if (bad) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) flags[blockIdx.x] = any;
+}
+
 // Deterministic pseudo-random values in [-scale, scale) (splitmix64 of the index): the
 // wavefield the autotuner times on, so that candidates run on data of a real run's
 // statistics rather than on the all-zero state of a fresh solver.
@@ -1434,6 +1449,26 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
       m->step += n;
       m->ckpt_valid = false;
     }
+  });
+}
+
+ovfem_status ovfem_check_finite(ovfem_solver* s, int32_t* finite) {
+  return guarded([&] {
+    require(s != nullptr && finite != nullptr, "ovfem_check_finite: NULL argument");
+    s->check_device();
+    const size_t nv = (size_t)s->n_shots * s->vec();
+    DevBuf<int> flags;
+    flags.alloc(2 * kFiniteBlocks);
+    nonfinite_kernel<<<kFiniteBlocks, 256, 0, s->stream>>>(s->u[s->buf_cur(s->phase)].p, nv, flags.p);
+    OVFEM_HIP(hipGetLastError());
+    nonfinite_kernel<<<kFiniteBlocks, 256, 0, s->stream>>>(s->u[s->buf_prev(s->phase)].p, nv, flags.p + kFiniteBlocks);
+    OVFEM_HIP(hipGetLastError());
+    std::vector<int> h(2 * kFiniteBlocks);
+    OVFEM_HIP(hipMemcpyAsync(h.data(), flags.p, h.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    OVFEM_HIP(hipStreamSynchronize(s->stream));
+    int bad = 0;
+    for (int f : h) bad |= f;
+    *finite = bad ? 0 : 1;
   });
 }
 

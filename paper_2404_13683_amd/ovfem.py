@@ -54,6 +54,7 @@ SIGNATURES = {
     "ovfem_batch_destroy": (_i32, [_vp]),
     "ovfem_batch_set_tuning": (_i32, [_vp, _i32]),
     "ovfem_batch_step": (_i32, [_vp, _i64]),
+    "ovfem_check_finite": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "ovfem_synchronize": (_i32, [_vp]),
 }
 
@@ -222,6 +223,13 @@ class Solver:
 
     def synchronize(self):
         _check(_LIB.ovfem_synchronize(self._h))
+
+    def check_finite(self):
+        """True if the current wavefield pair of every shot holds only finite values."""
+        v = _i32()
+        self._order_in()
+        _check(_LIB.ovfem_check_finite(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def matvec(self, u, out=None):
         import torch

@@ -151,3 +151,24 @@ def test_mostly_removed_voxels(prec):
     tr = s.get_traces().cpu().numpy()[0]
     if np.linalg.norm(ref) > 0:
         assert _rel(tr, ref) <= TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8"])
+def test_blow_up_check(prec):
+    """ovfem_check_finite: true along a normal run, false once a non-finite value is in
+    the wavefield pair (set on purpose through ovfem_set_wavefield), true again after
+    reset."""
+    w = _case(67, nt=30)
+    s = _solver(w, prec)
+    s.set_sources(w.src_node, w.src_comp, w.wavelet)
+    s.set_receivers(w.rec_node, w.nt)
+    s.step(w.nt)
+    assert s.check_finite()
+    for bad in (float("nan"), float("inf")):
+        un = s.get_wavefield(0).clone()
+        unm1 = s.get_wavefield(1).clone()
+        un[3 * (w.n_nodes // 2) + 1] = bad
+        s.set_wavefield(un, unm1, step=w.nt)
+        assert not s.check_finite()
+        s.reset()
+        assert s.check_finite()
