@@ -1,0 +1,91 @@
+"""GPU: the kernel combinations the other tests leave out.
+
+Every stepper kernel is instantiated per (path, digit stage count, element) and per
+damped/undamped step; these runs cover the damped kernels of the stage counts 4..7 and of
+the trilinear element on every path, and batches of trilinear solvers, against the
+oracle's damped stepper (trilinear or OVFEM) or against stepping alone.
+"""
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from paper_2404_13683_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _damped_case(seed=81, nt=200, element="ovfem"):
+    w = wl.layered_c2(nx=26, ny=22, nz=18, f0=30.0, nt=nt, seed=seed)
+    f0 = w.meta.get("f0", 30.0)
+    alpha, beta = oasm.rayleigh_coefficients(0.02, 0.8 * f0, 1.25 * f0)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt, alpha=alpha, beta=beta, element=element)
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    return w, alpha, beta, ref, u_ref
+
+
+def _solver(w, prec, alpha, beta, element="ovfem", stages=None):
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver(w.nx, w.ny, w.nz, w.h, precision=prec)
+    if element != "ovfem":
+        s.set_element(element)
+    if stages is not None:
+        s.set_stages(stages)
+    s.set_model(w.lam, w.mu, w.rho, w.solid)
+    s.set_fixed_nodes(w.fixed)
+    s.set_damping(alpha, beta)
+    s.set_dt(w.dt)
+    s.set_sources(w.src_node, w.src_comp, w.wavelet)
+    s.set_receivers(w.rec_node, w.nt)
+    return s
+
+
+def test_damped_kernels_of_every_stage_count():
+    """Damped runs with M = 4..8 digit stages: the error against the oracle's damped
+    stepper falls with M as in the undamped case (M >= 6 within the 1e-9 trace bar)."""
+    w, alpha, beta, ref, _ = _damped_case()
+    err = {}
+    for M in (4, 5, 6, 7, 8):
+        s = _solver(w, "int8", alpha, beta, stages=M)
+        s.step(w.nt)
+        err[M] = _rel(s.get_traces().cpu().numpy()[0], ref)
+        s.close()
+    print("damped traces vs the oracle per stage count:", {k: "%.2e" % v for k, v in err.items()})
+    for M in (6, 7, 8):
+        assert err[M] <= 1e-9
+    assert err[4] <= 1e-4 and err[5] <= 1e-6
+    assert err[4] > err[5] > err[6]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64-sf", "int8", "int8-bf16"])
+def test_damped_trilinear_on_every_path(prec):
+    w, alpha, beta, ref, u_ref = _damped_case(seed=82, element="trilinear")
+    s = _solver(w, prec, alpha, beta, element="trilinear")
+    s.step(w.nt)
+    et = _rel(s.get_traces().cpu().numpy()[0], ref)
+    eu = _rel(s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape), u_ref)
+    print("damped trilinear %s: traces %.3e wavefield %.3e" % (prec, et, eu))
+    assert et <= 1e-9 and eu <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64-sf", "int8"])
+def test_trilinear_batch_is_stepping_alone(prec):
+    from paper_2404_13683_amd.ovfem import Batch, Solver
+    doms = wl.uneven_domains_c3(n_domains=3, smallest=(10, 12, 9), largest=(26, 22, 16), f0=60.0, nt=50, n_rec=3)
+
+    def make(d):
+        s = Solver.from_workload(d, precision=prec, element="trilinear")
+        return s
+
+    alone = [make(d) for d in doms]
+    members = [make(d) for d in doms]
+    b = Batch(members)
+    b.step(50)
+    b.close()
+    for a, m in zip(alone, members):
+        a.step(50)
+        assert np.array_equal(a.get_traces().cpu().numpy(), m.get_traces().cpu().numpy())
+        assert np.array_equal(a.get_wavefield(0).cpu().numpy(), m.get_wavefield(0).cpu().numpy())
