@@ -2,8 +2,9 @@
 
 Every stepper kernel is instantiated per (path, digit stage count, element) and per
 damped/undamped step; these runs cover the damped kernels of the stage counts 4..7 and of
-the trilinear element on every path, and batches of trilinear solvers, against the
-oracle's damped stepper (trilinear or OVFEM) or against stepping alone.
+the trilinear element on every path, batches of trilinear solvers, and the adjoint with
+6 digit stages and of the damped trilinear recursion, against the oracle's (damped)
+stepper and adjoint or against stepping alone.
 """
 import numpy as np
 import pytest
@@ -89,3 +90,47 @@ def test_trilinear_batch_is_stepping_alone(prec):
         a.step(50)
         assert np.array_equal(a.get_traces().cpu().numpy(), m.get_traces().cpu().numpy())
         assert np.array_equal(a.get_wavefield(0).cpu().numpy(), m.get_wavefield(0).cpu().numpy())
+
+
+def _adjoint_case(seed, element="ovfem", zeta=0.0):
+    nx, ny, nz, nt = 12, 10, 9, 50
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    rho = rng.uniform(1900, 2400, shape)
+    vs = rng.uniform(500, 1100, shape)
+    lam, mu = wl.lame_from_velocities(2.0 * vs, vs, rho)
+    h = 4.0
+    dt = wl.stable_dt(h, lam * 1.2, mu * 1.2, rho)
+    f0 = 1.0 / (18 * dt)
+    alpha, beta = oasm.rayleigh_coefficients(zeta, 0.8 * f0, 1.25 * f0) if zeta else (0.0, 0.0)
+    src = np.array([wl.node_id(nx // 2, ny // 2, nz, nx, ny)], np.int64)
+    rec = wl.surface_nodes(rng, 5, nx, ny, nz, exclude=src)
+    w = wl.Workload("adjoint-combination", nx, ny, nz, h, lam, mu, rho, wl.box_fixed(nx, ny, nz), dt, nt, src,
+                    np.array([2], np.int32), np.array([0], np.int32), wl.ricker(nt, dt, f0)[None, :], rec)
+    mt = oasm.Model(lam * (1 + 0.1 * rng.standard_normal(shape)), mu, rho, h, w.fixed, dt, alpha=alpha, beta=beta,
+                    element=element)
+    d_obs, *_ = oasm.simulate(mt, nt, src, w.src_comp, w.wavelet, rec)
+    m = oasm.Model(lam, mu, rho, h, w.fixed, dt, alpha=alpha, beta=beta, element=element)
+    _, gl, gm = oasm.adjoint_gradient(m, nt, src, w.src_comp, w.wavelet, rec, d_obs)
+    return w, alpha, beta, d_obs, gl, gm
+
+
+@pytest.mark.parametrize("case", ["int8-M6", "trilinear-damped-fp64-sf", "trilinear-damped-int8"])
+def test_adjoint_combinations(case):
+    """The adjoint with 6 digit stages, and of the damped trilinear recursion, against the
+    oracle's discrete adjoint."""
+    import torch
+    if case == "int8-M6":
+        w, alpha, beta, d_obs, gl, gm = _adjoint_case(83)
+        s = _solver(w, "int8", alpha, beta, stages=6)
+    else:
+        prec = {"trilinear-damped-fp64-sf": "fp64-sf", "trilinear-damped-int8": "int8"}[case]
+        w, alpha, beta, d_obs, gl, gm = _adjoint_case(84, element="trilinear", zeta=0.05)
+        s = _solver(w, prec, alpha, beta, element="trilinear")
+    s.set_checkpointing(7, w.nt)
+    s.step(w.nt)
+    res = (s.get_traces() - torch.from_numpy(d_obs).cuda()[None]).contiguous()
+    g_lam, g_mu = (g.cpu().numpy() for g in s.adjoint(res))
+    el_, em_ = _rel(g_lam, gl), _rel(g_mu, gm)
+    print("adjoint %s: %.3e %.3e" % (case, el_, em_))
+    assert el_ <= 1e-9 and em_ <= 1e-9
