@@ -76,3 +76,41 @@ def test_product_path_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", text, re.M), f
                 assert not re.search(r"import_module\(\s*['\"]oracle|#include\s+[<\"][^>\"]*oracle", text), f
+
+
+@needs_lib
+def test_header_is_plain_c_and_links(tmp_path):
+    """The header compiles as C99 (no C++ in the ABI), a C program links against the
+    library, and its host-side validation answers before any device work."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "ovfem.h"
+int main(void) {
+  ovfem_solver* s = 0;
+  int32_t finite = 0;
+  int ok = ovfem_version() >= 200;
+  ok &= ovfem_create(0, 4, 4, 4, 1.0, 1, OVFEM_INT8, 0) == OVFEM_EINVAL;
+  ok &= ovfem_create(&s, 4, 4, 4, 1.0, 0, OVFEM_FP64, 0) == OVFEM_EINVAL && s == 0;
+  ok &= ovfem_step(0, 1) == OVFEM_EINVAL;
+  ok &= ovfem_check_finite(0, &finite) == OVFEM_EINVAL;
+  printf("%s|", ovfem_last_error());
+  ok &= ovfem_destroy(0) == OVFEM_OK;
+  printf("%d\n", ok);
+  return ok ? 0 : 1;
+}
+''')
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(LIB)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                        "-L", libdir, "-lovfem", "-Wl,-rpath," + libdir, "-Wl,-rpath,/opt/rocm/lib",
+                        "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, run.stdout + run.stderr
+    assert "NULL" in run.stdout
