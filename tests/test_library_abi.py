@@ -79,7 +79,7 @@ def test_product_path_does_not_use_the_oracle():
 
 
 @needs_lib
-def test_header_is_plain_c_and_links(tmp_path):
+def test_header_is_plain_c_and_links():
     """The header compiles as C99 (no C++ in the ABI), a C program links against the
     library, and its host-side validation answers before any device work."""
     import shutil
@@ -87,8 +87,10 @@ def test_header_is_plain_c_and_links(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    src = tmp_path / "abi.c"
-    src.write_text(r'''
+    work = os.path.join(PKG, "_build", "abi_c_test")  # the package's (ignored) build folder
+    os.makedirs(work, exist_ok=True)
+    src = os.path.join(work, "abi.c")
+    open(src, "w").write(r'''
 #include <stdio.h>
 #include "ovfem.h"
 int main(void) {
@@ -105,12 +107,12 @@ int main(void) {
   return ok ? 0 : 1;
 }
 ''')
-    exe = tmp_path / "abi"
+    exe = os.path.join(work, "abi")
     libdir = os.path.dirname(LIB)
-    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), src,
                         "-L", libdir, "-lovfem", "-Wl,-rpath," + libdir, "-Wl,-rpath,/opt/rocm/lib",
-                        "-o", str(exe)], capture_output=True, text=True)
+                        "-o", exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
-    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert run.returncode == 0, run.stdout + run.stderr
     assert "NULL" in run.stdout
