@@ -4,7 +4,8 @@ Every stepper kernel is instantiated per (path, digit stage count, element) and 
 damped/undamped step; these runs cover the damped kernels of the stage counts 4..7 and of
 the trilinear element on every path, batches of trilinear solvers, and the adjoint with
 6 digit stages and of the damped trilinear recursion, against the oracle's (damped)
-stepper and adjoint or against stepping alone.
+stepper and adjoint or against stepping alone; and a run whose precision and stage count
+change between steps.
 """
 import numpy as np
 import pytest
@@ -134,3 +135,26 @@ def test_adjoint_combinations(case):
     el_, em_ = _rel(g_lam, gl), _rel(g_mu, gm)
     print("adjoint %s: %.3e %.3e" % (case, el_, em_))
     assert el_ <= 1e-9 and em_ <= 1e-9
+
+
+def test_precision_switches_mid_run():
+    """Every step writes its tile exponents whatever the path, so the precision (and the
+    stage count) can change between steps: a run that switches fp64 -> int8 (M = 6) ->
+    fp64-sf -> int8-bf16 -> int8 matches the oracle's run."""
+    from paper_2404_13683_amd.ovfem import Solver
+    w = wl.layered_c2(nx=24, ny=20, nz=16, f0=30.0, nt=200, seed=85)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    ref, u_ref, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    s = Solver.from_workload(w, precision="fp64")
+    for prec, stages, n in (("fp64", None, 40), ("int8", 6, 40), ("fp64-sf", None, 40), ("int8-bf16", None, 40),
+                            ("int8", 8, 40)):
+        if prec == "int8-bf16":
+            s.set_stages(8)
+        s.set_precision(prec)
+        if stages is not None:
+            s.set_stages(stages)
+        s.step(n)
+    et = _rel(s.get_traces().cpu().numpy()[0], ref)
+    eu = _rel(s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape), u_ref)
+    print("precision switches: traces %.3e wavefield %.3e" % (et, eu))
+    assert et <= 1e-9 and eu <= 1e-9
