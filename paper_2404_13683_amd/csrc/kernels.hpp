@@ -806,9 +806,11 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 // The shots of one grid (A.n_units of them, laid out at fixed strides): one work-group
 // per tile and shot, work items remapped so each XCD takes a contiguous run.  The step
 // index is *step_base + step (step_base may be null), so a captured sequence of launches
-// can be replayed with a step base kept in device memory.
+// can be replayed with a step base kept in device memory.  The i8 kernels are held to
+// four waves per SIMD (128 registers): the damped and the 6-digit forms otherwise take
+// 129-131 and drop to three, which costs them 8-9 %.
 template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
+__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_INT8 ? 4 : 2))
     ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
   const int units = A.n_units > 1 ? A.n_units : 1;
