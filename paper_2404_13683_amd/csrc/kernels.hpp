@@ -158,7 +158,7 @@ struct NodeRef {
 __device__ inline NodeRef node_ref(const Geom& g, int X, int Y) {
   NodeRef r;
   r.xy_ok = X >= 0 && Y >= 0 && X <= g.nx && Y <= g.ny;
-  r.off = r.xy_ok ? (uint32_t)(24 * (X + (g.nx + 1) * Y)) : 0u;
+  r.off = r.xy_ok ? 24u * (uint32_t)(X + (g.nx + 1) * Y) : 0u;  // below 2^32 (checked at create)
   return r;
 }
 
@@ -182,7 +182,7 @@ struct ElemRef {
 __device__ inline ElemRef elem_ref(const Geom& g, int X, int Y) {
   ElemRef r;
   r.xy_ok = X >= 0 && Y >= 0 && X < g.nx && Y < g.ny;
-  r.off = r.xy_ok ? (uint32_t)(16 * (X + g.nx * Y)) : 0u;
+  r.off = r.xy_ok ? 16u * (uint32_t)(X + g.nx * Y) : 0u;
   return r;
 }
 
