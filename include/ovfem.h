@@ -40,7 +40,9 @@
  * data_ptr() of a torch tensor).  Uploads copy: the caller keeps ownership of every
  * buffer it passes and may free it when the call returns.  The solver owns all of its
  * device state.  All GPU work is enqueued on the stream given at creation; calls that
- * return data to the host, and ovfem_synchronize, wait for that stream.
+ * return data to the host, and ovfem_synchronize, wait for that stream.  Calls that
+ * allocate, copy or launch return OVFEM_ESTATE when the current HIP device is not the
+ * one the solver was created on (the library never switches devices itself).
  *
  * Errors: every call returns an ovfem_status (0 = success, negative = failure) and
  * never throws.  On failure the call has no effect on the solver, and

@@ -851,6 +851,7 @@ ovfem_status ovfem_set_sources(ovfem_solver* s, int32_t n, const int64_t* node, 
                                const int32_t* shot, const double* wavelet, int64_t nt) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_sources: solver is NULL");
+    s->check_device();
     require(n >= 0, "ovfem_set_sources: n < 0");
     require(n == 0 || (node && comp && wavelet && nt > 0), "ovfem_set_sources: missing arrays or nt <= 0");
     require((double)n * (double)std::max<int64_t>(nt, 1) < 2147483647.0, "ovfem_set_sources: table too large");
@@ -893,6 +894,7 @@ ovfem_status ovfem_set_sources(ovfem_solver* s, int32_t n, const int64_t* node, 
 ovfem_status ovfem_set_receivers(ovfem_solver* s, int32_t n, const int64_t* node, int64_t nt_max) {
   return guarded([&] {
     require(s != nullptr, "ovfem_set_receivers: solver is NULL");
+    s->check_device();
     require(n >= 0 && nt_max >= 0, "ovfem_set_receivers: negative count");
     require(n == 0 || node, "ovfem_set_receivers: node is NULL");
     require(nt_max < 2147483647 && (double)n * 3.0 * (double)nt_max < 2147483647.0,
@@ -967,6 +969,7 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
 ovfem_status ovfem_get_wavefield(ovfem_solver* s, int32_t which, double* out) {
   return guarded([&] {
     require(s != nullptr, "ovfem_get_wavefield: solver is NULL");
+    s->check_device();
     require(which == 0 || which == 1, "ovfem_get_wavefield: which must be 0 or 1");
     require(out != nullptr, "ovfem_get_wavefield: out is NULL");
     const int src = which == 0 ? s->buf_cur(s->phase) : s->buf_prev(s->phase);
@@ -995,6 +998,7 @@ ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double
 ovfem_status ovfem_get_traces(ovfem_solver* s, double* out) {
   return guarded([&] {
     require(s != nullptr, "ovfem_get_traces: solver is NULL");
+    s->check_device();
     require(out != nullptr || s->n_rec == 0 || s->rec_nt == 0, "ovfem_get_traces: out is NULL");
     const size_t n = (size_t)s->n_shots * s->n_rec * 3 * s->rec_nt;
     if (n > 0)

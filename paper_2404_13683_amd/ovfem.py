@@ -93,10 +93,12 @@ def _host(a, dtype):
     return a, a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _dev_f64(t, n, name):
+def _dev_f64(t, n, name, device):
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError("%s must be a contiguous CUDA float64 tensor" % name)
+    if t.device.index != device:
+        raise ValueError("%s is on cuda:%d, the solver on cuda:%d" % (name, t.device.index, device))
     if t.numel() != n:
         raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
     return ctypes.c_void_p(t.data_ptr())
@@ -110,6 +112,7 @@ class Solver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.device = torch.cuda.current_device()  # the library creates the solver there
         self.nx, self.ny, self.nz, self.h = int(nx), int(ny), int(nz), float(h)
         self.n_shots = int(n_shots)
         self.n_nodes = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
@@ -235,9 +238,9 @@ class Solver:
         import torch
         n = 3 * self.n_nodes
         if out is None:
-            out = torch.empty(n, dtype=torch.float64, device=u.device)
+            out = torch.empty(n, dtype=torch.float64, device=self.device)
         self._order_in()
-        _check(_LIB.ovfem_matvec(self._h, _dev_f64(u, n, "u"), _dev_f64(out, n, "out")))
+        _check(_LIB.ovfem_matvec(self._h, _dev_f64(u, n, "u", self.device), _dev_f64(out, n, "out", self.device)))
         self._order_out()
         return out
 
@@ -246,24 +249,25 @@ class Solver:
         import torch
         n = self.n_shots * 3 * self.n_nodes
         if out is None:
-            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            out = torch.empty(n, dtype=torch.float64, device=self.device)
         self._order_in()
-        _check(_LIB.ovfem_get_wavefield(self._h, int(which), _dev_f64(out, n, "out")))
+        _check(_LIB.ovfem_get_wavefield(self._h, int(which), _dev_f64(out, n, "out", self.device)))
         self._order_out()
         return out
 
     def set_wavefield(self, un, unm1, step=0):
         n = self.n_shots * 3 * self.n_nodes
         self._order_in()
-        _check(_LIB.ovfem_set_wavefield(self._h, _dev_f64(un, n, "un"), _dev_f64(unm1, n, "unm1"), int(step)))
+        _check(_LIB.ovfem_set_wavefield(self._h, _dev_f64(un, n, "un", self.device),
+                                        _dev_f64(unm1, n, "unm1", self.device), int(step)))
 
     def get_traces(self, out=None):
         import torch
         n = self.n_shots * self.n_rec * 3 * self.rec_nt
         if out is None:
-            out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")[:n]
+            out = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)[:n]
         self._order_in()
-        _check(_LIB.ovfem_get_traces(self._h, _dev_f64(out, n, "out") if n else None))
+        _check(_LIB.ovfem_get_traces(self._h, _dev_f64(out, n, "out", self.device) if n else None))
         self._order_out()
         return out.view(self.n_shots, self.n_rec, 3, self.rec_nt)
 
@@ -276,11 +280,11 @@ class Solver:
         n = self.n_shots * self.n_rec * 3 * self.rec_nt
         r = residual.reshape(-1)
         ne = self.nx * self.ny * self.nz
-        g_lam = torch.empty(ne, dtype=torch.float64, device="cuda")
-        g_mu = torch.empty(ne, dtype=torch.float64, device="cuda")
+        g_lam = torch.empty(ne, dtype=torch.float64, device=self.device)
+        g_mu = torch.empty(ne, dtype=torch.float64, device=self.device)
         self._order_in()
-        _check(_LIB.ovfem_adjoint(self._h, _dev_f64(r, n, "residual"), _dev_f64(g_lam, ne, "g_lam"),
-                                  _dev_f64(g_mu, ne, "g_mu")))
+        _check(_LIB.ovfem_adjoint(self._h, _dev_f64(r, n, "residual", self.device),
+                                  _dev_f64(g_lam, ne, "g_lam", self.device), _dev_f64(g_mu, ne, "g_mu", self.device)))
         self._order_out()
         shape = (self.nz, self.ny, self.nx)
         return g_lam.view(shape), g_mu.view(shape)

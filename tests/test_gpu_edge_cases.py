@@ -172,3 +172,24 @@ def test_blow_up_check(prec):
         assert not s.check_finite()
         s.reset()
         assert s.check_finite()
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding passes only contiguous float64 tensors of the right size on the
+    solver's device; anything else is refused before the library is called."""
+    import torch
+    w = _case(68, nt=10)
+    s = _solver(w, "int8")
+    n = 3 * w.n_nodes
+    good = torch.zeros(n, dtype=torch.float64, device="cuda")
+    assert s.device == torch.cuda.current_device()
+    bad = [torch.zeros(n, dtype=torch.float32, device="cuda"),  # dtype
+           torch.zeros(n, dtype=torch.float64),  # host memory
+           torch.zeros(2 * n, dtype=torch.float64, device="cuda")[::2],  # not contiguous
+           torch.zeros(n + 3, dtype=torch.float64, device="cuda")]  # size
+    for t in bad:
+        with pytest.raises((TypeError, ValueError)):
+            s.matvec(t)
+        with pytest.raises((TypeError, ValueError)):
+            s.set_wavefield(t, good)
+    assert torch.count_nonzero(s.matvec(good)) == 0
