@@ -834,6 +834,56 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_IN
 // run.  ovfem_batch_kernel takes one work item per work-group;
 // ovfem_batch_strided_kernel runs on a grid smaller than the work list and strides over
 // it (the grid size is then a multiple of 8, so a work-group stays on one XCD's run).
+// Unit v's argument record, read field by field through the constant address space:
+// the records are written by the host before the launch and never by a kernel, and
+// invariant loads let the compiler treat the fields as it treats kernel arguments (the
+// i8 batch kernel then fits in 128 registers instead of 144).
+__device__ inline KArgs load_unit(const KArgs* units, int v) {
+  static_assert(sizeof(KArgs) == 256, "load_unit copies every field of KArgs: keep the two in step");
+  using CK = const __attribute__((address_space(4))) KArgs;
+  CK* p = reinterpret_cast<CK*>(reinterpret_cast<uintptr_t>(units)) + v;
+  KArgs a;
+  a.g.nx = p->g.nx;
+  a.g.ny = p->g.ny;
+  a.g.nz = p->g.nz;
+  a.g.tz = p->g.tz;
+  a.g.tiles_x = p->g.tiles_x;
+  a.g.tiles_y = p->g.tiles_y;
+  a.g.chunks = p->g.chunks;
+  a.g.n_wg = p->g.n_wg;
+  a.u = p->u;
+  a.uprev = p->uprev;
+  a.unext = p->unext;
+  a.ku = p->ku;
+  a.mat = p->mat;
+  a.acoef = p->acoef;
+  a.exp_in = p->exp_in;
+  a.exp_out = p->exp_out;
+  a.alane = p->alane;
+  a.alane8 = p->alane8;
+  a.src_ptr = p->src_ptr;
+  a.src_node = p->src_node;
+  a.src_comp = p->src_comp;
+  a.src_row = p->src_row;
+  a.wavelet = p->wavelet;
+  a.rec_ptr = p->rec_ptr;
+  a.rec_node = p->rec_node;
+  a.rec_idx = p->rec_idx;
+  a.traces = p->traces;
+  a.src_nt = p->src_nt;
+  a.rec_nt = p->rec_nt;
+  a.step = p->step;
+  a.damp_b = p->damp_b;
+  a.damp_c1 = p->damp_c1;
+  a.damp_c2 = p->damp_c2;
+  a.n_units = p->n_units;
+  a.unit_u = p->unit_u;
+  a.unit_exp = p->unit_exp;
+  a.unit_src = p->unit_src;
+  a.unit_tr = p->unit_tr;
+  return a;
+}
+
 __device__ inline int find_unit(const int* unit_begin, int n_units, int item) {
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -845,13 +895,13 @@ __device__ inline int find_unit(const int* unit_begin, int n_units, int item) {
 }
 
 template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
+__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_INT8 ? 4 : 2))
     ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                        const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
   const int item = logical_tile(blockIdx.x, total);
   const int v = find_unit(unit_begin, n_units, item);
-  const KArgs A = units[v];
+  const KArgs A = load_unit(units, v);
   layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, item - unit_begin[v], s + A.step);
 }
 
@@ -863,7 +913,7 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
   for (int b = blockIdx.x; b < total; b += gridDim.x) {
     const int item = logical_tile(b, total);
     const int v = find_unit(unit_begin, n_units, item);
-    const KArgs A = units[v];
+    const KArgs A = load_unit(units, v);
     layer_tile<PATH, MODE, M, DAMP, false, ELEM>(A, item - unit_begin[v], s + A.step);
     __syncthreads();  // LDS is reused by the next work item
   }
