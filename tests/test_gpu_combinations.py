@@ -4,8 +4,8 @@ Every stepper kernel is instantiated per (path, digit stage count, element) and 
 damped/undamped step; these runs cover the damped kernels of the stage counts 4..7 and of
 the trilinear element on every path, batches of trilinear solvers, and the adjoint with
 6 digit stages and of the damped trilinear recursion, against the oracle's (damped)
-stepper and adjoint or against stepping alone; and a run whose precision and stage count
-change between steps.
+stepper and adjoint or against stepping alone; a run whose precision and stage count
+change between steps; and the batch kernels of every stage count against stepping alone.
 """
 import numpy as np
 import pytest
@@ -158,3 +158,29 @@ def test_precision_switches_mid_run():
     eu = _rel(s.get_wavefield(0).cpu().numpy().reshape(u_ref.shape), u_ref)
     print("precision switches: traces %.3e wavefield %.3e" % (et, eu))
     assert et <= 1e-9 and eu <= 1e-9
+
+
+@pytest.mark.parametrize("stages,damped", [(4, False), (5, False), (6, False), (7, False), (6, True)])
+def test_uneven_batch_per_stage_count(stages, damped):
+    """The batch kernels of every stage count (and the damped one with 6 digits) step an
+    uneven batch bitwise as each member steps alone."""
+    from paper_2404_13683_amd.ovfem import Batch, Solver
+    doms = wl.uneven_domains_c3(n_domains=3, smallest=(10, 12, 9), largest=(30, 26, 18), f0=60.0, nt=60, n_rec=3)
+
+    def make(d):
+        s = Solver.from_workload(d, precision="int8")
+        s.set_stages(stages)
+        if damped:
+            s.set_damping(0.5, 0.05 * d.dt)
+        return s
+
+    alone = [make(d) for d in doms]
+    members = [make(d) for d in doms]
+    b = Batch(members)
+    b.step(60)
+    b.close()
+    for a, m in zip(alone, members):
+        a.step(60)
+        assert np.array_equal(a.get_traces().cpu().numpy(), m.get_traces().cpu().numpy())
+        assert np.array_equal(a.get_wavefield(0).cpu().numpy(), m.get_wavefield(0).cpu().numpy())
+        assert np.array_equal(a.get_wavefield(1).cpu().numpy(), m.get_wavefield(1).cpu().numpy())
