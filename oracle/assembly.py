@@ -308,10 +308,11 @@ def dense_stiffness(lam, mu, h):
     return K
 
 
-def matvec_at_nodes(u, lam, mu, h, nodes):
+def matvec_at_nodes(u, lam, mu, h, nodes, solid=None):
     """(K u) at the listed nodes only: each from its (up to 8) touching elements.
 
-    u is the full nodal array (nz+1, ny+1, nx+1, 3); nodes are (k, j, i) triples.
+    u is the full nodal array (nz+1, ny+1, nx+1, 3); nodes are (k, j, i) triples;
+    elements with solid == 0 (removed voxels) contribute nothing, as in Model.
     Used to check full-size results on a sample of outputs.
     """
     Kl, Km = ovfem_reference()
@@ -322,6 +323,8 @@ def matvec_at_nodes(u, lam, mu, h, nodes):
             di, dj, dk = alpha & 1, (alpha >> 1) & 1, (alpha >> 2) & 1
             ei, ej, ek = i - di, j - dj, k - dk
             if not (0 <= ei < nx and 0 <= ej < ny and 0 <= ek < nz):
+                continue
+            if solid is not None and not solid[ek, ej, ei]:
                 continue
             ue = np.concatenate([u[ek + ((b >> 2) & 1), ej + ((b >> 1) & 1), ei + (b & 1)] for b in range(8)])
             ye = h * (lam[ek, ej, ei] * (Kl @ ue) + mu[ek, ej, ei] * (Km @ ue))

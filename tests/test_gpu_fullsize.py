@@ -57,11 +57,8 @@ def _flat(w, pts):
     return np.array([i + (w.nx + 1) * (j + (w.ny + 1) * k) for k, j, i in pts], np.int64)
 
 
-def _masked(w):
-    if w.solid is None:
-        return w.lam, w.mu
-    s = w.solid.astype(bool)
-    return np.where(s, w.lam, 0.0), np.where(s, w.mu, 0.0)
+def _solid(w):
+    return None if w.solid is None else w.solid.astype(bool)
 
 
 def check_matvec_sampled(w, solver, prec, seed=5):
@@ -82,8 +79,7 @@ def check_matvec_sampled(w, solver, prec, seed=5):
     pts = sample_nodes(w, seed=seed)
     idx = torch.from_numpy(_flat(w, pts)).cuda()
     got = ku.view(-1, 3).index_select(0, idx).cpu().numpy()
-    lam, mu = _masked(w)
-    ref = oasm.matvec_at_nodes(u, lam, mu, w.h, pts)
+    ref = oasm.matvec_at_nodes(u, w.lam, w.mu, w.h, pts, solid=_solid(w))
     err = _rel(got, ref)
     print("%s %s sampled matvec (%d nodes) rel L2 %.3e" % (w.name, prec, len(pts), err))
     assert err <= MATVEC_TOL
@@ -100,9 +96,8 @@ def check_one_step_sampled(w, solver, prec, shot=0):
     pts = sample_nodes(w, n_random=200, seed=n)
     flat = _flat(w, pts)
     got = solver.get_wavefield(0).view(-1, nn, 3)[shot].cpu().numpy()[flat]
-    lam, mu = _masked(w)
-    ku = oasm.matvec_at_nodes(un, lam, mu, w.h, pts)
-    mass = oasm.nodal_mass(w.rho, w.h, None if w.solid is None else w.solid.astype(bool))
+    ku = oasm.matvec_at_nodes(un, w.lam, w.mu, w.h, pts, solid=_solid(w))
+    mass = oasm.nodal_mass(w.rho, w.h, _solid(w))
     free = oasm.free_mask(w.fixed, mass)
     sel = np.asarray(w.src_shot) == shot
     F = np.zeros((len(pts), 3))

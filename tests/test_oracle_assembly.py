@@ -118,3 +118,41 @@ def test_err_measure_definition():
     obs[0, 1] += 1.0
     # channel 0: 1 / 5, channel 1: 0  -> mean 0.1
     assert asm.err_measure(obs, ref) == pytest.approx(0.1)
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3), (1, 1, 1), (2, 1, 3), (4, 4, 4)])
+def test_sampled_matvec_equals_the_assembled_matvec_at_every_node(shape):
+    """matvec_at_nodes, the per-node loop that checks full-size results on sampled outputs,
+    gives (K u) of the assembled operator (Sec. 2, Eqs. (2) and (5)) at every node of
+    small grids: every corner, edge, face and interior node, with voxels removed.  It is
+    checked against Model.K (slice assembly, itself pinned to the plain-loop dense matrix)
+    and, on the smallest grids, against the dense matrix directly."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    h = 0.9
+    lam = rng.uniform(1, 3, (nz, ny, nx))
+    mu = rng.uniform(1, 3, (nz, ny, nx))
+    rho = rng.uniform(1, 2, (nz, ny, nx))
+    solid = rng.uniform(size=(nz, ny, nx)) > 0.3
+    if solid.size > 1:
+        solid.flat[0] = False  # a hole at a grid corner, whatever the draw
+    u = rng.standard_normal((nz + 1, ny + 1, nx + 1, 3))
+    model = asm.Model(lam, mu, rho, h, np.zeros((nz + 1, ny + 1, nx + 1), np.uint8), 1.0, solid=solid)
+    ref = model.K(u)
+    nodes = [(k, j, i) for k in range(nz + 1) for j in range(ny + 1) for i in range(nx + 1)]
+    got = asm.matvec_at_nodes(u, lam, mu, h, nodes, solid=solid)
+    want = np.array([ref[k, j, i] for k, j, i in nodes])
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 1e-14 * scale
+    # the unmasked arrays with the mask given, and the masked arrays without it, agree
+    got2 = asm.matvec_at_nodes(u, model.lam, model.mu, h, nodes)
+    assert np.abs(got2 - want).max() <= 1e-14 * scale
+    if nx * ny * nz <= 12:
+        K = asm.dense_stiffness(model.lam, model.mu, h)
+        dense = (K @ u.reshape(-1)).reshape(-1, 3)
+        flat = [i + (nx + 1) * (j + (ny + 1) * k) for k, j, i in nodes]
+        assert np.abs(got - dense[flat]).max() <= 1e-13 * scale
+    # a removed voxel is really left out: unmasked lam/mu give a different answer
+    if not solid.all():
+        full = asm.matvec_at_nodes(u, lam, mu, h, nodes)
+        assert np.abs(full - want).max() > 1e-6 * scale
