@@ -1,26 +1,29 @@
 """Benchmark of the fused OVFEM stepper on one MI355X.
 
-Workload (one step = one pass of the whole hot path: gather, element products,
-assembly and the central-difference update, with source injection and receivers):
-three horizontal layers on 256 x 256 x 128 voxels (8.4 M elements, ~25 M free
-DOF), h = 5 m, Vs 300/800/2000 m/s, Vp = 2 Vs, rho 1800/2100/2500 kg/m^3, seeded
-+-10 % Gaussian-correlated (L = 50 m) lam/mu perturbation, Ricker 5 Hz, dt at
-0.5 x CFL.  Inputs are synthetic and already resident in HBM when timing starts.
+Workload (default; one step = one pass of the whole hot path: gather, element products,
+assembly and the central-difference update, with source injection and receivers): the
+512 x 512 x 256 voxel model (67 M voxels, h = 2 m) with seeded fractal surface topography
+(+-40 m, air voxels removed) over a nested three-material basin (Vs 200/600/1500 m/s,
+Vp = 2 Vs, rho 1800/2100/2500 kg/m^3), Ricker 5 Hz, dt at 0.5 x CFL, 4000 steps: the
+largest single-GPU configuration of the method.  Inputs are synthetic and already
+resident in HBM when timing starts.
 
-Both element-product paths run from reset for warmup + steps time steps: the
-plain FP64 path and the INT8 matrix-core path.  `value` is the INT8 path's
-DOF-updates per second; the FP64 path, their ratio and the INT8-vs-FP64 receiver
-trace error are reported beside it.  The CPU oracle is timed on a bounded sample
-of the same workload on the host's cores.
+Each element-product path (INT8 digit slices on the matrix cores, dense FP64 as the
+paper evaluates it, sum-factorised FP64) runs from reset for warmup + steps timed time
+steps; `value` is the INT8 path's DOF-updates per second.  Then, untimed, every path runs
+the workload's whole length from reset again (4000 steps for the default), and the
+INT8-vs-FP64 receiver-trace error over that run is reported: the accuracy condition of
+the metric holds for traces after all steps, whatever --steps is.  The CPU oracle is
+timed on a bounded sample on the host's cores.
 
 Other workloads (parity cases, one JSON line each, not the headline):
+  --workload c2          256 x 256 x 128, three layers with perturbations, 2000 steps
   --workload c3-shots    64 shots on 128 x 128 x 64 in one launch per step
   --workload c3-uneven   16 layered domains of uneven size, one batched launch per step
-  --workload c5          512 x 512 x 256 fractal topography over a basin, air removed
-  --workload c5-slab     512 x 512 x 32 of the same recipe: one GPU's share of c5 split 8 ways
+  --workload c5-slab     512 x 512 x 32 of the c5 recipe: one GPU's share of c5 split 8 ways
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload NAME]
-(--steps defaults to the workload's run length: 2000 for c2, 1000 for c3, 4000 for c5)
+(--steps defaults to the workload's run length: 4000 for c5, 2000 for c2, 1000 for c3)
 """
 import argparse
 import hashlib
@@ -42,14 +45,16 @@ INT8_OPS_PER_ELEMENT = 2 * 48 * 24 * 8    # [AL; AM] (48 x 24) times 8 digit sli
 FP64_FLOP_PER_ELEMENT = 2 * 2 * 24 * 24   # AL u and AM u in FP64
 
 
-# run length of each workload: the trace comparison between the paths covers the whole run
-# (in the first few hundred steps of the large models the receivers see only the scheme's
-# numerical precursor, amplitudes far below any arrival, where relative errors mean little)
+# run length of each workload: the untimed parity leg compares the paths' traces over it
 FULL_STEPS = {"c2": 2000, "c3-shots": 1000, "c3-uneven": 1000, "c5": 4000, "c5-slab": 4000}
 
 KERNEL_SOURCES = ["paper_2404_13683_amd/csrc/kernels.hpp", "paper_2404_13683_amd/csrc/refmat.hpp"]
 EQUAL_ACCURACY = os.path.join(ROOT, "tests", "golden", "equal_dispersion_accuracy.json")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "layer_kernel_counters_layered_256x256x128.txt")
+# rocprofv3 counter summaries of the stepper kernels, per workload
+COUNTERS_FILES = {
+    "c2": os.path.join(ROOT, "profiles", "layer_kernel_counters_layered_256x256x128.txt"),
+    "c5": os.path.join(ROOT, "profiles", "layer_kernel_counters_topography_512x512x256.txt"),
+}
 
 
 def kernel_sha():
@@ -59,18 +64,26 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path_name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor)."""
-    if not os.path.exists(COUNTERS_FILE):
+def _counter_values(workload):
+    """Key = value pairs of the workload's committed counter summary, if it was taken on the
+    current kernel source (else None)."""
+    f = COUNTERS_FILES.get(workload)
+    if not f or not os.path.exists(f):
         return None
     kv = {}
-    for line in open(COUNTERS_FILE):
-        line = line.strip()
-        if "=" in line and not line.startswith("#"):
+    for line in open(f):
+        line = line.split("#", 1)[0].strip()
+        if "=" in line:
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_sha") != kernel_sha():
+    return kv if kv.get("kernel_sha") == kernel_sha() else None
+
+
+def measured_traffic(workload, path_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel factors), if taken on the current kernel source."""
+    kv = _counter_values(workload)
+    if kv is None:
         return None
     try:
         f = float(kv["%s_fetch_kib" % path_name]) * float(kv["fetch_factor"])
@@ -78,6 +91,30 @@ def measured_traffic(path_name):
     except KeyError:
         return None
     return (f + w) * 1024.0
+
+
+def profile_counters(workload, path_name):
+    """Busy fractions of the stepper kernel from the committed counter summary."""
+    kv = _counter_values(workload)
+    if kv is None:
+        return None
+    out = {}
+    for key in ("valu_busy", "mfma_busy", "waves_per_simd", "wait_frac"):
+        if "%s_%s" % (path_name, key) in kv:
+            out[key] = float(kv["%s_%s" % (path_name, key)])
+    return out or None
+
+
+def limiter_text(frac_of_copy, counters):
+    """What bounds the kernel, from the live bandwidth and the committed counters."""
+    if frac_of_copy >= 0.8:
+        return "HBM: %.0f %% of a plain copy's bandwidth" % (100 * frac_of_copy)
+    if counters and "valu_busy" in counters:
+        return ("instruction issue, not HBM (%.0f %% of a plain copy's bandwidth): VALU busy %.2f, "
+                "MFMA busy %.2f, %.1f waves per SIMD (rocprofv3 counters)"
+                % (100 * frac_of_copy, counters["valu_busy"], counters.get("mfma_busy", 0.0),
+                   counters.get("waves_per_simd", 0.0)))
+    return None
 
 
 def copy_probe(nbytes):
@@ -113,26 +150,6 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return bw
 
 
-def profile_counters(path_name):
-    """Busy fractions of the stepper kernel from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source."""
-    if not os.path.exists(COUNTERS_FILE):
-        return None
-    kv = {}
-    for line in open(COUNTERS_FILE):
-        line = line.split("#", 1)[0].strip()
-        if "=" in line:
-            k, v = line.split("=", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_sha") != kernel_sha():
-        return None
-    out = {}
-    for key in ("valu_busy", "mfma_busy", "waves_per_simd", "wait_frac"):
-        if "%s_%s" % (path_name, key) in kv:
-            out[key] = float(kv["%s_%s" % (path_name, key)])
-    return out or None
-
-
 def trace_errors(a, b):
     """a against the reference b, both [..., receiver, component, step]: the pooled relative
     L2, the largest per-channel relative L2 over channels whose norm is at least 1e-6 of the
@@ -140,7 +157,11 @@ def trace_errors(a, b):
     sum_t (a - b)^2 / sum_t b^2, channels with a zero reference left out)."""
     a = np.asarray(a).reshape(-1, np.shape(a)[-1])
     b = np.asarray(b).reshape(-1, np.shape(b)[-1])
-    pooled = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return {"trace_rel_l2": None, "per_channel_max_rel_l2": None, "err_eq18": None,
+                "max_abs_diff": float(np.abs(a - b).max()), "note": "all reference traces are zero"}
+    pooled = float(np.linalg.norm(a - b) / nb)
     cn = np.linalg.norm(b, axis=1)
     sel = cn >= 1e-6 * cn.max()
     per = float(np.max(np.linalg.norm((a - b)[sel], axis=1) / cn[sel]))
@@ -149,11 +170,13 @@ def trace_errors(a, b):
     return {"trace_rel_l2": pooled, "per_channel_max_rel_l2": per, "err_eq18": err18}
 
 
-def algorithmic_bytes(nx, ny, nz, shots=1):
-    """Bytes a step must move: per shot u^n, u^{n-1} read and u^{n+1} written (72 B per node);
-    once, dt^2/m per node (8 B) and lam, mu per element (16 B)."""
-    nodes = (nx + 1) * (ny + 1) * (nz + 1)
-    return 72 * nodes * shots + 8 * nodes + 16 * nx * ny * nz
+def algorithmic_bytes(w):
+    """Bytes a step must move (free nodes and solid elements only): per free node and shot
+    u^n, u^{n-1} read and u^{n+1} written (72 B); per free node dt^2/m (8 B); per solid
+    element lam, mu (16 B)."""
+    free_nodes = w.free_dof() // 3
+    solid = w.n_elements if w.solid is None else int(np.count_nonzero(w.solid))
+    return 72 * free_nodes * w.n_shots + 8 * free_nodes + 16 * solid
 
 
 def _timed(step, warmup, steps):
@@ -170,35 +193,49 @@ def _timed(step, warmup, steps):
     return e0.elapsed_time(e1) / max(steps, 1)
 
 
-def time_path(wl, prec, warmup, steps, autotune=True, chunk_planes=0, stages=8, element="ovfem"):
-    """One solver (all shots of the workload): ms per step and the traces."""
-    from paper_2404_13683_amd.ovfem import Solver
-    s = Solver.from_workload(wl, precision=prec, receivers_nt=warmup + steps, element=element)
-    if prec == "int8":
-        s.set_stages(stages)
-    if chunk_planes:
-        s.set_tuning(chunk_planes=chunk_planes)
-    elif autotune:
-        s.autotune(steps=20)
-    tuning = s.get_tuning()
-    s.reset()
-    ms = _timed(s.step, warmup, steps)
-    traces = s.get_traces().cpu().numpy()
-    s.close()
-    return ms, traces, tuning
+class PathRun:
+    """The solvers of one element-product path for a workload (one solver with all shots,
+    or a batch of uneven solvers), kept open between the timed and the full-length legs."""
+
+    def __init__(self, wls, prec, rec_nt, batched, autotune=True, chunk_planes=0, stages=8, element="ovfem"):
+        from paper_2404_13683_amd.ovfem import Batch, Solver
+        self.solvers = [Solver.from_workload(w, precision=prec, receivers_nt=rec_nt, element=element)
+                        for w in wls]
+        self.batch = Batch(self.solvers) if batched else None
+        for s in self.solvers:
+            if prec == "int8":
+                s.set_stages(stages)
+            if not batched:
+                if chunk_planes:
+                    s.set_tuning(chunk_planes=chunk_planes)
+                elif autotune:
+                    s.autotune(steps=20)
+        self.tuning = None if batched else self.solvers[0].get_tuning()
+
+    def step(self, n):
+        if self.batch is not None:
+            self.batch.step(n)
+        else:
+            for s in self.solvers:
+                s.step(n)
+
+    def reset(self):
+        for s in self.solvers:
+            s.reset()
+
+    def traces(self, nt):
+        return np.concatenate([s.get_traces().cpu().numpy()[..., :nt].reshape(-1, nt) for s in self.solvers])
+
+    def close(self):
+        if self.batch is not None:
+            self.batch.close()
+        for s in self.solvers:
+            s.close()
 
 
-def time_batch(wls, prec, warmup, steps):
-    """A batch of solvers of uneven size stepped together."""
-    from paper_2404_13683_amd.ovfem import Batch, Solver
-    sols = [Solver.from_workload(w, precision=prec, receivers_nt=warmup + steps) for w in wls]
-    b = Batch(sols)
-    ms = _timed(b.step, warmup, steps)
-    traces = np.concatenate([s.get_traces().cpu().numpy().reshape(-1, warmup + steps) for s in sols])
-    b.close()
-    for s in sols:
-        s.close()
-    return ms, traces, None
+def time_run(run, warmup, steps):
+    run.reset()
+    return _timed(run.step, warmup, steps)
 
 
 def cpu_baseline(wl, budget_s=15.0, label=None):
@@ -239,6 +276,40 @@ def cpu_baseline(wl, budget_s=15.0, label=None):
                                               len(os.sched_getaffinity(0)))}
 
 
+def cpu_sample(name, wls):
+    """(workload, label) the oracle is timed on: the first one-shot model of the workload, or,
+    for the 512 x 512 x 256 model (whose host step would need ~50 GB of temporaries), the 32
+    element layers just below its lowest air voxel (all solid, through the basin)."""
+    import dataclasses
+
+    from paper_2404_13683_amd import workloads
+    w = wls[0]
+    if name != "c5":
+        return w, None
+    kz = 32
+    air_layers = np.nonzero((w.solid == 0).any(axis=(1, 2)))[0]
+    k0 = max(0, (int(air_layers.min()) if air_layers.size else w.nz) - kz)
+
+    def remap(nodes):
+        out = []
+        for nd in np.asarray(nodes, np.int64):
+            i, j, k = nd % (w.nx + 1), (nd // (w.nx + 1)) % (w.ny + 1), nd // ((w.nx + 1) * (w.ny + 1))
+            if k0 <= k <= k0 + kz:
+                out.append(workloads.node_id(i, j, k - k0, w.nx, w.ny))
+        return np.array(out, np.int64)
+
+    # the model's source, moved to the top centre of the slab
+    src = np.array([workloads.node_id(w.nx // 2, w.ny // 2, kz, w.nx, w.ny)], np.int64)
+    layers = slice(k0, k0 + kz)
+    slab = dataclasses.replace(w, nz=kz, lam=w.lam[layers], mu=w.mu[layers], rho=w.rho[layers],
+                               solid=None if w.solid is None else w.solid[layers],
+                               fixed=workloads.box_fixed(w.nx, w.ny, kz), src_node=src,
+                               src_comp=w.src_comp[:len(src)], src_shot=w.src_shot[:len(src)],
+                               wavelet=w.wavelet[:len(src)], rec_node=remap(w.rec_node))
+    return slab, ("element layers %d..%d (all solid, through the basin) of the 512x512x256 topography model "
+                  "(%d free DOF)" % (k0, k0 + kz - 1, slab.free_dof()))
+
+
 def make_workload(name, nt):
     """(list of workloads, description, batched?) for a workload name."""
     from paper_2404_13683_amd import workloads
@@ -256,8 +327,8 @@ def make_workload(name, nt):
                     % sum(w.free_dof() for w in ws)), True
     if name == "c5":
         w = workloads.topography_c5(nt=nt)
-        return [w], ("topography-basin-512x512x256 (67M voxels, %d free DOF, air removed), h=2 m, dt=%.4e s"
-                     % (w.free_dof(), w.dt)), False
+        return [w], ("topography-basin-512x512x256 (67M voxels, %d free DOF, air removed), h=2 m, Ricker 5 Hz, "
+                     "dt=%.4e s" % (w.free_dof(), w.dt)), False
     if name == "c5-slab":
         # one GPU's share of the 512 x 512 x 256 model split eight ways along z
         w = workloads.topography_c5(nz=32, nt=nt)
@@ -270,16 +341,18 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: the workload's own run length, 2000 for c2, 1000 for "
-                         "c3-shots and c3-uneven, 4000 for c5)")
+                    help="timed steps (default: the workload's own run length, 4000 for c5, 2000 for c2, "
+                         "1000 for c3-shots and c3-uneven)")
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--paths", default="fp64,int8,fp64-sf")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3-shots", "c3-uneven", "c5", "c5-slab"])
+    ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c3-shots", "c3-uneven", "c5-slab"])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--chunk-planes", type=int, default=0, help="fixed z-chunk depth instead of autotuning")
     ap.add_argument("--no-equal-accuracy", action="store_true", help="skip the trilinear comparison")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the untimed full-length trace comparison between the paths")
     ap.add_argument("--stage-sweep", action="store_true",
                     help="also time the INT8 path with 4..7 digit stages (accuracy/speed trade, Table 3)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
@@ -292,33 +365,31 @@ def main():
               "model or its shots across GPUs" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    full = FULL_STEPS[args.workload]
     if args.steps is None:
-        args.steps = FULL_STEPS[args.workload]
+        args.steps = full
 
     import torch
 
     torch.cuda.set_device(0)
-    nt = args.warmup + args.steps
-    wls, desc, batched = make_workload(args.workload, nt)
+    nt_timed = args.warmup + args.steps
+    rec_nt = max(nt_timed, full)
+    wls, desc, batched = make_workload(args.workload, rec_nt)
     free_dof = sum(w.free_dof() * w.n_shots for w in wls)
-    n_elem = sum(w.nx * w.ny * w.nz * w.n_shots for w in wls)
-    bytes_step = sum(algorithmic_bytes(w.nx, w.ny, w.nz, w.n_shots) for w in wls)
+    n_elem = sum(w.n_elements * w.n_shots for w in wls)
+    bytes_step = sum(algorithmic_bytes(w) for w in wls)
     paths = args.paths.split(",")
-    res = {}
+    runs, res = {}, {}
     for p in paths:
-        if batched:
-            ms, tr, tuning = time_batch(wls, p, args.warmup, args.steps)
-        else:
-            ms, tr, tuning = time_path(wls[0], p, args.warmup, args.steps, autotune=not args.no_autotune,
-                                       chunk_planes=args.chunk_planes)
-        res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "traces": tr, "tuning": tuning}
+        runs[p] = PathRun(wls, p, rec_nt, batched, autotune=not args.no_autotune, chunk_planes=args.chunk_planes)
+        ms = time_run(runs[p], args.warmup, args.steps)
+        res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "tuning": runs[p].tuning}
         print("[bench] %s %s: %.4f ms/step, %.4e DOF-updates/s, tuning %s"
-              % (args.workload, p, ms, res[p]["value"], tuning), file=sys.stderr, flush=True)
+              % (args.workload, p, ms, res[p]["value"], runs[p].tuning), file=sys.stderr, flush=True)
     head = "int8" if "int8" in res else paths[0]
     ms = res[head]["ms_per_step"]
     hbm = bytes_step / (ms * 1e-3)
     sha = kernel_sha()
-    traffic = measured_traffic(head) if args.workload == "c2" else None
     out = {
         "metric": METRIC,
         "value": res[head]["value"],
@@ -328,7 +399,6 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
-        "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int8-digits(i8-mfma,int32-acc,exact)+f64" if head == "int8" else
                  ("int8-digits(bf16-mfma,exact)+f64" if head == "int8-bf16" else "f64"),
@@ -337,63 +407,84 @@ def main():
                    "domains": [[w.nx, w.ny, w.nz, w.n_shots] for w in wls] if len(wls) > 1 else
                    [wls[0].nx, wls[0].ny, wls[0].nz, wls[0].n_shots]},
         "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": hbm / HBM_PEAK, "traffic": traffic, "kernel_sha": sha,
-                     "algorithmic_bytes_per_step": bytes_step,
+                     "frac": hbm / HBM_PEAK, "traffic": measured_traffic(args.workload, head), "kernel_sha": sha,
+                     "algorithmic_bytes_per_launch": bytes_step,
                      "mfma_frac_int8_peak": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / INT8_PEAK
                      if head.startswith("int8") else None},
     }
     if "fp64" in res:
         f = res["fp64"]
         out["fp64_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"],
-                            "traffic": measured_traffic("fp64") if args.workload == "c2" else None,
+                            "traffic": measured_traffic(args.workload, "fp64"),
                             "fp64_frac": FP64_FLOP_PER_ELEMENT * n_elem / (f["ms_per_step"] * 1e-3) / FP64_PEAK,
                             "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK,
                             "tuning": f["tuning"]}
+        if head != "fp64":
+            out["int8_speedup_vs_fp64"] = f["ms_per_step"] / ms
     if "fp64-sf" in res:
         f = res["fp64-sf"]
         out["fp64_sf_path"] = {"ms_per_step": f["ms_per_step"], "value": f["value"],
-                               "traffic": measured_traffic("fp64-sf") if args.workload == "c2" else None,
+                               "traffic": measured_traffic(args.workload, "fp64-sf"),
                                "hbm_frac": bytes_step / (f["ms_per_step"] * 1e-3) / HBM_PEAK, "tuning": f["tuning"],
                                "note": "the OVFEM product sum-factorised in FP64 (a stronger FP64 baseline than the "
                                        "dense form the paper compares against)"}
-        if "fp64" in res:
-            out["fp64_sf_path"]["trace_rel_l2_vs_fp64"] = float(
-                np.linalg.norm(f["traces"] - res["fp64"]["traces"]) / np.linalg.norm(res["fp64"]["traces"]))
-    if "fp64" in res and head != "fp64":
-        out["int8_vs_fp64"] = {"speedup": res["fp64"]["ms_per_step"] / res[head]["ms_per_step"],
-                               **trace_errors(res[head]["traces"], res["fp64"]["traces"]),
-                               "steps_compared": nt}
+    if not args.no_full_run and "fp64" in res:
+        # untimed: every path over the workload's whole run from reset, traces compared
+        tr = {}
+        for p in paths:
+            runs[p].reset()
+            runs[p].step(full)
+            tr[p] = runs[p].traces(full)
+            print("[bench] full run of %d steps on %s done" % (full, p), file=sys.stderr, flush=True)
+        for p in paths:
+            if p != "fp64":
+                key = "int8_vs_fp64" if p == head else "%s_vs_fp64" % p.replace("-", "_")
+                out[key] = dict(trace_errors(tr[p], tr["fp64"]), steps_compared=full,
+                                run="untimed, every path from reset over the workload's %d steps" % full)
+    for p in paths:
+        runs[p].close()
+    del runs
     copy_bw = copy_bandwidth()
     out["roofline"]["copy_GBps"] = copy_bw / 1e9
     out["roofline"]["frac_of_copy"] = hbm / copy_bw
-    out["roofline"]["counters"] = profile_counters(head) if args.workload == "c2" else None
-    if head.startswith("int8"):
-        out["roofline"]["limiter"] = ("not HBM: the element phase's instruction issue and dependency latency; "
-                                      "timing-only copies of the kernel put the matrix-core digit products at "
-                                      "29 % of the step, the node phase at 12 %, the FP64 recombination at 11 %")
-    if args.stage_sweep and not batched and "fp64" in res:
+    counters = profile_counters(args.workload, head)
+    out["roofline"]["counters"] = counters
+    out["roofline"]["limiter"] = limiter_text(hbm / copy_bw, counters)
+    if args.stage_sweep and "fp64" in res:
         sweep = []
+        ref = PathRun(wls, "fp64", rec_nt, batched, autotune=not args.no_autotune, chunk_planes=args.chunk_planes)
+        ref.reset()
+        ref.step(full)
+        b = ref.traces(full)
+        ref.close()
         for M in (4, 5, 6, 7):
-            ms_m, tr_m, tun_m = time_path(wls[0], "int8", args.warmup, args.steps,
-                                          autotune=not args.no_autotune, chunk_planes=args.chunk_planes, stages=M)
-            b = res["fp64"]["traces"]
+            r = PathRun(wls, "int8", rec_nt, batched, autotune=not args.no_autotune,
+                        chunk_planes=args.chunk_planes, stages=M)
+            ms_m = time_run(r, args.warmup, args.steps)
+            r.reset()
+            r.step(full)
+            tr_m = r.traces(full)
+            r.close()
             sweep.append({"stages": M, "ms_per_step": ms_m, "value": free_dof / (ms_m * 1e-3),
                           "trace_rel_l2_vs_fp64": float(np.linalg.norm(tr_m - b) / np.linalg.norm(b)),
-                          "tuning": tun_m})
+                          "tuning": r.tuning})
             print("[bench] stages %d: %.4f ms/step" % (M, ms_m), file=sys.stderr, flush=True)
         out["stage_sweep"] = sweep
-    if args.workload == "c2" and "int8" in res and not args.no_equal_accuracy:
+    if not batched and "int8" in res and not args.no_equal_accuracy and args.workload in ("c2", "c5"):
         # Sec. 3's comparison with the trilinear element at equal accuracy: the trilinear
-        # FP64 kernel on the same model, and the mesh refinement it needs for the same
+        # FP64 kernels on the same model, and the mesh refinement it needs for the same
         # numerical dispersion (oracle Bloch analysis, stored with the script that wrote it)
-        ms_t, _, tun_t = time_path(wls[0], "fp64", args.warmup, args.steps, autotune=not args.no_autotune,
-                                   chunk_planes=args.chunk_planes, element="trilinear")
-        ms_ts, _, _ = time_path(wls[0], "fp64-sf", args.warmup, args.steps, autotune=not args.no_autotune,
-                                chunk_planes=args.chunk_planes, element="trilinear")
+        tri = {}
+        for p in ("fp64", "fp64-sf"):
+            r = PathRun(wls, p, rec_nt, False, autotune=not args.no_autotune, chunk_planes=args.chunk_planes,
+                        element="trilinear")
+            tri[p] = (time_run(r, args.warmup, args.steps), r.tuning)
+            r.close()
         fx = json.load(open(EQUAL_ACCURACY))
         row = [r for r in fx["rows"] if r["ppw_ovfem"] == 10][0]
+        ms_t, ms_ts = tri["fp64"][0], tri["fp64-sf"][0]
         out["equal_accuracy"] = {
-            "trilinear_fp64_ms_per_step": ms_t, "trilinear_tuning": tun_t,
+            "trilinear_fp64_ms_per_step": ms_t, "trilinear_tuning": tri["fp64"][1],
             "trilinear_fp64_sf_ms_per_step": ms_ts,
             "dispersion_h_ratio": row["h_ratio"], "refinement_cost_factor": row["cost_factor"],
             "at": "10 points per S wavelength, RMS phase error %.2e" % row["rms_phase_error"],
@@ -405,7 +496,8 @@ def main():
         print("[bench] trilinear fp64: %.4f ms/step, fp64-sf: %.4f ms/step" % (ms_t, ms_ts), file=sys.stderr,
               flush=True)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_budget, label=desc)
+        sample, label = cpu_sample(args.workload, wls)
+        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_budget, label=label)
     print(json.dumps(out))
 
 

@@ -19,12 +19,17 @@
 //   * FP64 path: one thread per element, dense 24 x 24 products in FP64 with the
 //     integer matrices as compile-time constants (the paper's "OVFEM FP64").
 //   * INT8 paths (Sec. 2, Eqs. (10)-(17), reworked for CDNA4).  u is written as
-//     2^(E-QB) q, q = floor(u 2^(QB-E)) an integer with |q| < 2^QB, under one
-//     power-of-two exponent E per tile (the paper scales each element by s_e; a
-//     shared exponent lets a node's slices be computed once for its 8 elements).
-//     q is split into M balanced base-256 digits d_j in [-128, 127], QB = 8M - 2
-//     (M = 8 by default: 62 bits, every value within 2^9 of the tile maximum exact; the
-//     paper: 8 sign-magnitude base-128 digits of a 56-bit integer), and the digit
+//     2^(S-QB) q, q = u 2^(QB-S) rounded to the nearest integer, |q| <= 2^QB, under
+//     one power-of-two exponent S per element layer of the work-group (the paper
+//     scales each element by its own s_e; an exponent shared by the 17 x 17 x 2
+//     staged nodes of a layer lets a node's slices be computed once for the 4
+//     elements of the layer that touch it).  S is the smallest power of two above
+//     every staged value, taken from the staged values themselves (see
+//     StagingExponent); a node plane is staged again only when the next layer's S
+//     differs.  q is split into M balanced base-256 digits d_j in [-128, 127],
+//     QB = 8M - 2 (M = 8 by default: 62 bits, so every entry is represented to
+//     2^(S-63) absolutely, 2^-61 relative to the layer maximum; the paper: 8
+//     sign-magnitude base-128 digits of a 56-bit integer), and the digit
 //     products with the 48 x 24 integer matrix [AL; AM] run on the matrix cores, digits
 //     taken pairwise from the top.  PATH_INT8 uses v_mfma_i32_16x16x32_i8:
 //     C = A d_hi, C <<= 8, C += A d_lo, exact in INT32 since
@@ -35,7 +40,7 @@
 //     384 * 128 * 256 + 384 * 255 < 2^24 (exact in FP32); the +128 bias drops out
 //     because each row of K sums to zero (rigid translations).  Both give the same
 //     pair sums, which are recombined in FP64 (Horner with factor 2^16) and scaled by
-//     h lam_e / 256 * 2^(E-QB) and h mu_e / 128 * 2^(E-QB).
+//     h lam_e / 256 * 2^(S-QB) and h mu_e / 128 * 2^(S-QB).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,7 +76,13 @@ struct Stages {
 };
 constexpr int FPLANE = 3 * PN * PN;        // doubles per staged FP64 plane
 constexpr int NEXTRA = PN * PN - NTHR;     // staged nodes beyond one per thread (33)
-constexpr int EXP_NONE = -1000000;         // exponent of an all-zero tile
+// Staging exponent of the INT8 paths.  S >= EXP_FLOOR keeps the scale factors
+// h lam / 256 2^(S-QB) normal (values below 2^(EXP_FLOOR-QB-1) round to 0); a layer
+// keeps the previous layer's S while L <= S <= L + EXP_SLACK (L: the exact exponent of
+// the layer's staged maximum), else S = L + EXP_HEAD and the shared plane is staged again.
+constexpr int EXP_FLOOR = -900;
+constexpr int EXP_HEAD = 0;
+constexpr int EXP_SLACK = 0;
 
 static_assert(kMaxRowAbs * 128 * 256 + kMaxRowAbs * 255 < (1 << 24),
               "digit-pair sums must be exact in FP32");
@@ -105,8 +116,6 @@ struct KArgs {
   double* ku;             // MODE_MATVEC output K u, [node][3]
   const double* mat;      // [element][2] = (h lam / 256, h mu / 128), 0 for removed voxels
   const double* acoef;    // dt^2 / m per node, 0 where the node does not move
-  const int* exp_in;      // per tile: exponent e with max |u^n| < 2^e (INT8 path)
-  int* exp_out;           // per tile: same for u^{n+1} (MODE_STEP)
   const v4u* alane;       // INT8 A operands, [3 row tiles][64 lanes] x 8 bf16
   const uint64_t* alane8; // I8 A operands, [3 row tiles][64 lanes] x 8 int8
   const int* src_ptr;     // [n_wg + 1] CSR of sources per tile
@@ -131,7 +140,6 @@ struct KArgs {
   // unit v at these element offsets from the pointers above (0 units taken as 1)
   int n_units;
   long long unit_u;    // nodal vectors: u, uprev, unext
-  int unit_exp;        // exp_in, exp_out
   int unit_src;        // src_ptr
   long long unit_tr;   // traces
 };
@@ -198,20 +206,26 @@ __device__ inline uint32_t bf16_pair(float lo, float hi) {
   return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
 }
 
-// Stage one node's INT8 slices: q ~ u 2^(62-E) per component, the biased bytes
+// q = u 2^(QB-S) rounded to the nearest integer (|u| < 2^S, so |q| <= 2^QB <= 2^62), as
+// a two's-complement 64-bit integer.  q = hd 2^32 + lo with hd = floor(q 2^-32) and
+// 0 <= lo < 2^32: q is an integer, so both steps are exact and lo converts in range.
+template <int QB>
+__device__ inline uint64_t quantise(double u, int S) {
+  const double x = rint(ldexp(u, QB - S));
+  const double hd = floor(x * 0x1p-32);                 // exact, |hd| <= 2^30
+  const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);  // exact, in [0, 2^32)
+  return ((uint64_t)(uint32_t)(int)hd << 32) | lo_u;
+}
+
+// Stage one node's INT8 slices: q = rint(u 2^(62-S)) per component, the biased bytes
 // e_j = d_j + 128 of q + sum_j 128 * 256^j, and per digit pair p the bf16 B-operand
 // words (c0, c1), (c2, 0) of 256 d_{2p+1} (hi) and of e_{2p} (lo).  dst points at the
 // node's first word in its row ([p][hi/lo][x][2] with x stride 2 dwords).
-__device__ inline void stage_digits(const D3& u, int E, uint32_t* dst) {
+__device__ inline void stage_digits(const D3& u, int S, uint32_t* dst) {
   uint32_t lo[3], hi[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    // q = floor(x) up to one unit (the low word is truncated after at most one
-    // rounding of x - hd 2^32), |q| <= 2^62
-    const double x = ldexp(u.v[c], QBITS - E);
-    const double hd = floor(x * 0x1p-32);                 // exact, |hd| <= 2^30
-    const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);  // in [0, 2^32)
-    const uint64_t q = ((uint64_t)(uint32_t)(int)hd << 32) | lo_u;  // two's complement
+    const uint64_t q = quantise<QBITS>(u.v[c], S);
     const uint64_t d = q + 0x8080808080808080ull;        // bytes are d_j + 128
     lo[c] = (uint32_t)d;
     hi[c] = (uint32_t)(d >> 32);
@@ -241,26 +255,23 @@ __device__ inline void stage_digits(const D3& u, int E, uint32_t* dst) {
     }
 }
 
-// i8 form of the node staging with M digits: q = floor(u 2^(8M-2-E)), |q| < 2^(8M-2),
+// i8 form of the node staging with M digits: q = rint(u 2^(8M-2-S)), |q| <= 2^(8M-2),
 // written as M balanced base-256 digits (the bytes of q + sum_j 128 * 256^j, minus 128;
 // the bytes above M are then exactly 128); per digit j the word
 // (d_j(c0), d_j(c1), d_j(c2), 0) is written at dst[j * PN].
 template <int M>
-__device__ inline void stage_digits_i8(const D3& u, int E, uint32_t* dst) {
+__device__ inline void stage_digits_i8(const D3& u, int S, uint32_t* dst) {
   constexpr int QB = Stages<M>::QB;
   uint32_t lo[3], hi[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double x = ldexp(u.v[c], QB - E);
     if constexpr (M <= 4) {
-      const int q = (int)floor(x);  // |q| < 2^30
+      const int q = (int)rint(ldexp(u.v[c], QB - S));  // |q| <= 2^30
       lo[c] = ((uint32_t)q + 0x80808080u) ^ 0x80808080u;
       hi[c] = 0u;
       continue;
     }
-    const double hd = floor(x * 0x1p-32);
-    const uint32_t lo_u = (uint32_t)fma(hd, -0x1p32, x);
-    const uint64_t q = ((uint64_t)(uint32_t)(int)hd << 32) | lo_u;
+    const uint64_t q = quantise<QB>(u.v[c], S);
     const uint64_t d = q + 0x8080808080808080ull;  // bytes d_j + 128
     lo[c] = (uint32_t)d ^ 0x80808080u;              // bytes d_j (two's complement)
     hi[c] = (uint32_t)(d >> 32) ^ 0x80808080u;
@@ -393,24 +404,29 @@ __device__ inline double rows_down(double v) {
   return __hiloint2double((int)h[1], (int)l[1]);
 }
 
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+// Magnitude key of a double: its high word with the sign cleared.  Keys order as the
+// magnitudes do (not strictly), and the biased exponent b = key >> 20 bounds every
+// value of a smaller or equal key: |v| < 2^(max(b, 1) - 1022).
+__device__ inline uint32_t mag_key(double v) { return (uint32_t)__double2hiint(v) & 0x7fffffffu; }
+
+__device__ inline uint32_t node_key(const D3& v) {
+  return max(mag_key(v.v[0]), max(mag_key(v.v[1]), mag_key(v.v[2])));
 }
 
-// Work-group max of |u| over owned nodes -> tile exponent e with max < 2^e.
-__device__ inline void write_tile_exponent(double local_max, int* dst, double* red) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  local_max = wave_max(local_max);
-  if (lane == 0) red[w] = local_max;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    int e = EXP_NONE;
-    if (m > 0.0) frexp(m, &e);
-    *dst = e;
-  }
+// Smallest exponent e >= EXP_FLOOR with |v| < 2^e for every v whose key is <= key.
+__device__ inline int key_exponent(uint32_t key) {
+  return max(max((int)(key >> 20), 1) - 1022, EXP_FLOOR);
+}
+
+// Maximum over the wave (every lane gets it): DPP within rows of 16, then the four rows.
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));   // quad [1,0,3,2]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));   // quad [2,3,0,1]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));  // row_ror 4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));  // row_ror 8
+  const uint32_t r0 = __builtin_amdgcn_readlane((int)v, 0), r1 = __builtin_amdgcn_readlane((int)v, 16);
+  const uint32_t r2 = __builtin_amdgcn_readlane((int)v, 32), r3 = __builtin_amdgcn_readlane((int)v, 48);
+  return max(max(r0, r1), max(r2, r3));
 }
 
 // One work-group tile (tile index wg of its unit) of one time step (or one matvec).
@@ -436,7 +452,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   // in-plane node sums: lsum[q] from elements of row q, usum[q-1] from elements of row q-1
   __shared__ double lsum[TE * 3 * TE];  // [q][c][p], q = 0..15
   __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
-  __shared__ double red[4];
+  __shared__ __attribute__((aligned(16))) uint32_t keys[2][4];  // per wave: magnitude keys of staged planes
   constexpr bool F64 = is_f64_path(PATH);
   __shared__ __attribute__((aligned(16))) double matl[F64 ? 2 : 2 * NTHR];  // slices: [b][a] material
   constexpr int RING_BYTES = F64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * St::PLANE * 4);
@@ -444,19 +460,8 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
 
-  // ---- tile exponent (INT8): max over the 27 tiles owning the staged nodes
-  int E = 0;
-  if (!F64) {
-    int e = EXP_NONE;
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int X = tx + dx, Y = ty + dy, Z = tzc + dz;
-          if (X >= 0 && Y >= 0 && Z >= 0 && X < g.tiles_x && Y < g.tiles_y && Z < g.chunks)
-            e = max(e, A.exp_in[X + g.tiles_x * (Y + g.tiles_y * Z)]);
-        }
-    E = e == EXP_NONE ? 0 : e;
-  }
+  // INT8 staging exponent S of the current element layer (uniform over the work-group)
+  int S = 0;
   v8bf a_frag[3];
   long a_frag8[3];
   if (PATH == PATH_BF16) {
@@ -494,58 +499,86 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 #pragma unroll
   for (int i = 0; i < 4; ++i) top_i[i][0] = top_i[i][1] = top_i[i][2] = 0.0;
   double2 mat_next;
-  double tile_max = 0.0;
   const int src_lo = A.src_ptr[wg], src_hi = A.src_ptr[wg + 1];
   const int rec_lo = A.rec_ptr[wg], rec_hi = A.rec_ptr[wg + 1];
 
   const int nrel = z1 - z0 + 2;  // staged planes z0-1 .. z1
-  auto fetch = [&](int rel) {
+  // node values of staged plane rel (rel 0 = plane z0-1): the main node, and the extra
+  // node of the threads that have one (0 elsewhere)
+  auto load_plane = [&](int rel, D3& m, D3& x) {
     const int Z = z0 - 1 + rel;
     const bool z_ok = Z >= 0 && Z <= g.nz;
     const unsigned char* plane = u_base + (size_t)(z_ok ? Z : 0) * plane_bytes;
-    u_main_next = load_node(plane, main_ref, z_ok);
-    if (has_extra) u_extra_next = load_node(plane, extra_ref, z_ok);
+    m = load_node(plane, main_ref, z_ok);
+    if (has_extra) x = load_node(plane, extra_ref, z_ok);
     if constexpr (DAMP) {
       // stage w = u^n + b (u^n - u^{n-1}); the owned nodes' u^n is reloaded in the
       // node phase
       const unsigned char* pplane = up_base + (size_t)(z_ok ? Z : 0) * plane_bytes;
       const D3 pm = load_node(pplane, main_ref, z_ok);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) u_main_next.v[c] = fma(A.damp_b, u_main_next.v[c] - pm.v[c], u_main_next.v[c]);
+      for (int c = 0; c < 3; ++c) m.v[c] = fma(A.damp_b, m.v[c] - pm.v[c], m.v[c]);
       if (has_extra) {
         const D3 px = load_node(pplane, extra_ref, z_ok);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          u_extra_next.v[c] = fma(A.damp_b, u_extra_next.v[c] - px.v[c], u_extra_next.v[c]);
+        for (int c = 0; c < 3; ++c) x.v[c] = fma(A.damp_b, x.v[c] - px.v[c], x.v[c]);
       }
     }
   };
+  auto fetch = [&](int rel) { load_plane(rel, u_main_next, u_extra_next); };
   auto fetch_mat = [&](int k) {
     const bool z_ok = k >= 0 && k < g.nz;
     mat_next = load_material(mat_base + (size_t)(z_ok ? k : 0) * layer_bytes, elem, z_ok);
   };
-  auto stage = [&](int slot) {
+  auto stage = [&](int slot, const D3& m, const D3& x) {
     if (F64) {
       double* P = ringf + slot * FPLANE;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) P[(c * PN + mq) * PN + mp] = u_main_next.v[c];
+      for (int c = 0; c < 3; ++c) P[(c * PN + mq) * PN + mp] = m.v[c];
       if (has_extra)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) P[(c * PN + xq) * PN + xp] = u_extra_next.v[c];
+        for (int c = 0; c < 3; ++c) P[(c * PN + xq) * PN + xp] = x.v[c];
     } else if (PATH == PATH_BF16) {
       uint32_t* P = ringd + slot * DPLANE;
-      stage_digits(u_main_next, E, P + mq * DROW + 2 * mp);
-      if (has_extra) stage_digits(u_extra_next, E, P + xq * DROW + 2 * xp);
+      stage_digits(m, S, P + mq * DROW + 2 * mp);
+      if (has_extra) stage_digits(x, S, P + xq * DROW + 2 * xp);
     } else {
       uint32_t* P = ringd + slot * St::PLANE;
-      stage_digits_i8<M>(u_main_next, E, P + mq * St::ROW + mp);
-      if (has_extra) stage_digits_i8<M>(u_extra_next, E, P + xq * St::ROW + xp);
+      stage_digits_i8<M>(m, S, P + mq * St::ROW + mp);
+      if (has_extra) stage_digits_i8<M>(x, S, P + xq * St::ROW + xp);
     }
   };
+  // work-group maximum of the keys written by the four waves into keys[slot]
+  auto read_keys = [&](int slot) -> uint32_t {
+    const uint4 k4 = *reinterpret_cast<const uint4*>(keys[slot]);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)max(max(k4.x, k4.y), max(k4.z, k4.w)));
+  };
 
-  fetch(0);
-  stage(0);
-  fetch(1);
+  // Staging exponent (INT8).  Layer it (planes rel it, it+1) needs every staged value
+  // below 2^S; L(it) = key_exponent of the larger key of the two planes is the exact
+  // bound.  key_top: the key of plane it+1 while layer it runs.
+  uint32_t key_top = 0;
+  bool restage = false;  // plane it (already staged for layer it-1) must be staged again
+  if (F64) {
+    fetch(0);
+    stage(0, u_main_next, u_extra_next);
+    fetch(1);
+  } else {
+    D3 m0, x0 = {{0.0, 0.0, 0.0}};
+    load_plane(0, m0, x0);
+    fetch(1);
+    const uint32_t k0 = wave_max_u32(max(node_key(m0), node_key(x0)));
+    const uint32_t k1 = wave_max_u32(max(node_key(u_main_next), node_key(u_extra_next)));
+    if (lane == 0) {
+      keys[0][wave] = k0;
+      keys[1][wave] = k1;
+    }
+    __syncthreads();
+    const uint32_t K0 = read_keys(0);
+    key_top = read_keys(1);
+    S = key_exponent(max(K0, key_top)) + EXP_HEAD;
+    stage(0, m0, x0);
+  }
   fetch_mat(z0 - 1);
 
   for (int it = 0; it + 1 < nrel; ++it) {
@@ -553,7 +586,12 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     const int bot = it & 1, top = (it + 1) & 1;
     u_own_bot = u_own_top;
     u_own_top = u_main_next;
-    stage(top);
+    if (!F64 && restage) {
+      D3 rm, rx = {{0.0, 0.0, 0.0}};
+      load_plane(it, rm, rx);
+      stage(bot, rm, rx);
+    }
+    stage(top, u_main_next, u_extra_next);
     const double2 mat_e = mat_next;
     if (!F64) {
       matl[2 * t] = mat_e.x;
@@ -714,7 +752,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
           }
           // output s = 4 * row tile + reg: s < 6 rows of AL, s >= 6 rows of AM;
           // dk = (s % 6) / 3, c = s % 3, at corner G + 4 dk
-          const double sl = ldexp(me.x, E - QB), sm = ldexp(me.y, E - QB);
+          const double sl = ldexp(me.x, S - QB), sm = ldexp(me.y, S - QB);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             ybot[c] = R[c] * sl + R[6 + c] * sm;
@@ -742,8 +780,23 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
         }
         __builtin_amdgcn_sched_barrier(0);  // keep tile rows apart: bounds live registers
       }
+      // key of the plane fetched for the next layer (its loads had the element phase to land)
+      if (it + 2 < nrel) {
+        const uint32_t kk = wave_max_u32(max(node_key(u_main_next), node_key(u_extra_next)));
+        if (lane == 0) keys[0][wave] = kk;
+      }
     }
     __syncthreads();
+
+    if (!F64 && it + 2 < nrel) {
+      // exponent of the next layer (planes it+1, it+2); a change restages plane it+1
+      // (its values are reloaded when the next layer starts)
+      const uint32_t key_new = read_keys(0);
+      const int L = key_exponent(max(key_top, key_new));
+      key_top = key_new;
+      restage = L > S || S - L > EXP_SLACK;
+      if (restage) S = L + EXP_HEAD;
+    }
 
     // ---- node phase for plane Z = k (owned when it >= 1)
     if constexpr (LATE) load_node_state();
@@ -782,14 +835,6 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
         o[0] = un[0];
         o[1] = un[1];
         o[2] = un[2];
-        if constexpr (DAMP) {
-          // the next step stages w^{n+1} = u^{n+1} + b (u^{n+1} - u^n): its tile maximum
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            tile_max = fmax(tile_max, fabs(fma(A.damp_b, un[c] - u_own_bot.v[c], un[c])));
-        } else {
-          tile_max = fmax(tile_max, fmax(fabs(un[0]), fmax(fabs(un[1]), fabs(un[2]))));
-        }
         for (int r = rec_lo; r < rec_hi; ++r)
           if (A.rec_node[r] == (int)nid && step < A.rec_nt) {
             double* tr = A.traces + (long long)A.rec_idx[r] * 3 * A.rec_nt + step;
@@ -800,7 +845,6 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       }
     }
   }
-  if (MODE == MODE_STEP) write_tile_exponent(tile_max, A.exp_out + wg, red);
 }
 
 // The shots of one grid (A.n_units of them, laid out at fixed strides): one work-group
@@ -820,8 +864,6 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_IN
     A.u += v * A.unit_u;
     A.uprev += v * A.unit_u;
     A.unext += v * A.unit_u;
-    A.exp_in += v * A.unit_exp;
-    A.exp_out += v * A.unit_exp;
     A.src_ptr += v * A.unit_src;
     A.traces += v * A.unit_tr;
   }
@@ -839,7 +881,7 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_IN
 // invariant loads let the compiler treat the fields as it treats kernel arguments (the
 // i8 batch kernel then fits in 128 registers instead of 144).
 __device__ inline KArgs load_unit(const KArgs* units, int v) {
-  static_assert(sizeof(KArgs) == 256, "load_unit copies every field of KArgs: keep the two in step");
+  static_assert(sizeof(KArgs) == 240, "load_unit copies every field of KArgs: keep the two in step");
   using CK = const __attribute__((address_space(4))) KArgs;
   CK* p = reinterpret_cast<CK*>(reinterpret_cast<uintptr_t>(units)) + v;
   KArgs a;
@@ -857,8 +899,6 @@ __device__ inline KArgs load_unit(const KArgs* units, int v) {
   a.ku = p->ku;
   a.mat = p->mat;
   a.acoef = p->acoef;
-  a.exp_in = p->exp_in;
-  a.exp_out = p->exp_out;
   a.alane = p->alane;
   a.alane8 = p->alane8;
   a.src_ptr = p->src_ptr;
@@ -878,7 +918,6 @@ __device__ inline KArgs load_unit(const KArgs* units, int v) {
   a.damp_c2 = p->damp_c2;
   a.n_units = p->n_units;
   a.unit_u = p->unit_u;
-  a.unit_exp = p->unit_exp;
   a.unit_src = p->unit_src;
   a.unit_tr = p->unit_tr;
   return a;
@@ -922,32 +961,6 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
 // Adds n to the device step base (last node of a captured block of steps).
 static __global__ void ovfem_advance_step_kernel(long long* step_base, long long n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
-}
-
-// Tile exponents of a nodal vector u, or with up of u + b (u - up) (the vector a damped
-// step stages), in the stepper's tiling.
-static __global__ void __launch_bounds__(NTHR) ovfem_exponent_kernel(Geom g, const double* u, const double* up, double b,
-                                                               int* exp_out) {
-  __shared__ double red[4];
-  const int wg = blockIdx.x;
-  const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
-  const int t = threadIdx.x, ta = t & 15, tb = t >> 4;
-  const int X = tx * TN + ta, Y = ty * TN + tb;
-  const int z0 = tzc * g.tz, z1 = min(z0 + g.tz, g.nz + 1);
-  double m = 0.0;
-  if (ta < TN && tb < TN && X <= g.nx && Y <= g.ny)
-    for (int Z = z0; Z < z1; ++Z) {
-      const long long o = 3 * ((long long)X + (long long)(g.nx + 1) * ((long long)Y + (long long)(g.ny + 1) * Z));
-      const double* p = u + o;
-      if (up) {
-        const double* q = up + o;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) m = fmax(m, fabs(fma(b, p[c] - q[c], p[c])));
-      } else {
-        m = fmax(m, fmax(fabs(p[0]), fmax(fabs(p[1]), fabs(p[2]))));
-      }
-    }
-  write_tile_exponent(m, exp_out + wg, red);
 }
 
 // Per-element gradient terms of the discrete adjoint: for every solid element e,

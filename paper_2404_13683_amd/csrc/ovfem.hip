@@ -300,14 +300,10 @@ struct ovfem_solver {
   // state, [shot][node][3] per buffer: at phase ph, u^n is u[buf_cur(ph)] and u^{n-1} is
   // u[buf_prev(ph)]; a step writes u^{n+1} into u[buf_next(ph)] and moves to phase
   // buf_next(ph).  Undamped: two buffers, u^{n+1} over u^{n-1}.  Damped: three
-  // (neighbouring work-groups still read the halo of u^{n-1}).  expo[b] holds the tile
-  // exponents of the staged vector of buffer b (u^n, or w^n when damped), [shot][tile].
+  // (neighbouring work-groups still read the halo of u^{n-1}).
   DevBuf<double> u[3];
-  DevBuf<int> expo[3];
   int phase = 0;
-  bool exp_valid = false;
   double alpha = 0.0, beta = 0.0;  // Rayleigh damping C = alpha M + beta K
-  DevBuf<int> expo_tmp;          // exponents of a matvec operand
   DevBuf<double> mat, acoef;     // mat: [element][2] = (h lam / 256, h mu / 128)
   DevBuf<uint32_t> alane_bf16;
   DevBuf<uint64_t> alane_i8;
@@ -347,7 +343,7 @@ struct ovfem_solver {
     (void)hipStreamSynchronize(stream);
     drop_graphs();
     for (auto* b : {&u[0], &u[1], &u[2], &mat, &acoef, &wavelet, &traces, &ckpt}) b->free();
-    for (auto* b : {&expo[0], &expo[1], &expo[2], &expo_tmp, &unit_begin}) b->free();
+    unit_begin.free();
     src.free();
     rec.free();
     alane_bf16.free();
@@ -406,29 +402,6 @@ struct ovfem_solver {
     OVFEM_HIP(hipMemcpyAsync(acoef.p, a.data(), n_nodes * sizeof(double), hipMemcpyHostToDevice, stream));
     OVFEM_HIP(hipStreamSynchronize(stream));
     acoef_dirty = false;
-  }
-
-  // tile exponents of v (or, with vp, of v + b (v - vp)) for every shot
-  void launch_exponents(const Geom& g, const double* v, int* dst, int shots, const double* vp = nullptr,
-                        double b = 0.0) {
-    for (int s = 0; s < shots; ++s) {
-      ovfem_exponent_kernel<<<g.n_wg, NTHR, 0, stream>>>(g, v + (size_t)s * vec(), vp ? vp + (size_t)s * vec() : nullptr,
-                                                          b, dst + (size_t)s * g.n_wg);
-      OVFEM_HIP(hipGetLastError());
-    }
-  }
-  // exponents of the vector the next step stages
-  void state_exponents() {
-    if (damped() && !dt_set) {  // the staged vector depends on beta / dt
-      exp_valid = false;
-      return;
-    }
-    const int c = buf_cur(phase), p = buf_prev(phase);
-    if (damped())
-      launch_exponents(geom, u[c].p, expo[c].p, n_shots, u[p].p, damp_b());
-    else
-      launch_exponents(geom, u[c].p, expo[c].p, n_shots);
-    exp_valid = true;
   }
 
   // source lists of every (shot, tile) for tiling g; rows index the wavelet table
@@ -499,8 +472,6 @@ struct ovfem_solver {
     A.unext = u[x].p + (size_t)shot * vec();
     A.mat = mat.p;
     A.acoef = acoef.p;
-    A.exp_in = expo[c].p + (size_t)shot * geom.n_wg;
-    A.exp_out = expo[x].p + (size_t)shot * geom.n_wg;
     if (damped()) {
       const double ad = damp_a();
       A.damp_b = damp_b();
@@ -546,7 +517,6 @@ struct ovfem_solver {
       KArgs A = shot_args(0, ph);
       A.n_units = n_shots;
       A.unit_u = (long long)vec();
-      A.unit_exp = geom.n_wg;
       A.unit_src = geom.n_wg + 1;
       A.unit_tr = (long long)n_rec * 3 * rec_nt;
       launch_unit<MODE_STEP>(form(), A, base, step_arg, st);
@@ -591,7 +561,6 @@ struct ovfem_solver {
     if (traces.p) OVFEM_HIP(hipMemsetAsync(traces.p, 0, traces.n * sizeof(double), stream));
     phase = 0;
     step = 0;
-    state_exponents();
     ckpt_valid = ckpt_every > 0;
     ckpt_form = form_code();
   }
@@ -600,7 +569,6 @@ struct ovfem_solver {
     require(model_set, "ovfem_step: model not set", OVFEM_ESTATE);
     require(dt_set, "ovfem_step: dt not set", OVFEM_ESTATE);
     refresh_acoef();
-    if (!exp_valid) state_exponents();
     refresh_tables();
   }
 
@@ -637,39 +605,27 @@ struct ovfem_solver {
     }
   }
 
-  // change the z-chunk depth: new tiling, tile lists and exponents; the state is kept
+  // change the z-chunk depth: new tiling and tile lists; the state is kept
   void retile(int planes) {
     const Geom g = make_geom(nx, ny, nz, planes);
-    DevBuf<int> e0, e1, e2, et;
     SourceTables st;
     ReceiverTables rt;
     try {
-      e0.alloc((size_t)n_shots * g.n_wg);
-      e1.alloc((size_t)n_shots * g.n_wg);
-      if (u[2].p) e2.alloc((size_t)n_shots * g.n_wg);
-      et.alloc(g.n_wg);
       st = build_sources(g, src_node_h, src_comp_h, src_shot_h);
       rt = build_receivers(g, rec_node_h);
     } catch (...) {
-      for (auto* b : {&e0, &e1, &e2, &et}) b->free();
       st.free();
       rt.free();
       throw;
     }
     OVFEM_HIP(hipStreamSynchronize(stream));
-    std::swap(expo[0], e0);
-    std::swap(expo[1], e1);
-    std::swap(expo[2], e2);
-    std::swap(expo_tmp, et);
     std::swap(src, st);
     std::swap(rec, rt);
-    for (auto* b : {&e0, &e1, &e2, &et}) b->free();
     st.free();
     rt.free();
     geom = g;
     chunk_planes = planes;
-    state_exponents();
-    ckpt_valid = false;  // the INT8 exponent granularity follows the tiling
+    ckpt_valid = false;  // INT8 results depend on the tiling (the staging exponent's blocks)
     invalidate_launches();
     OVFEM_HIP(hipStreamSynchronize(stream));
   }
@@ -727,9 +683,6 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
       s->u[1].alloc((size_t)n_shots * s->vec());
       s->mat.alloc(2 * s->n_elem);
       s->acoef.alloc(s->n_nodes);
-      s->expo[0].alloc((size_t)n_shots * g.n_wg);
-      s->expo[1].alloc((size_t)n_shots * g.n_wg);
-      s->expo_tmp.alloc(g.n_wg);
       s->step_base.alloc(1);
       upload(s->alane_bf16, make_alane_bf16(OVFEM_ELEMENT_OVFEM), s->stream);
       upload(s->alane_i8, make_alane_i8(OVFEM_ELEMENT_OVFEM), s->stream);
@@ -843,7 +796,6 @@ ovfem_status ovfem_set_dt(ovfem_solver* s, double dt) {
     s->dt_set = true;
     s->acoef_dirty = true;
     s->invalidate_launches();  // the damping coefficients depend on dt
-    s->exp_valid = s->exp_valid && !s->damped();
   });
 }
 
@@ -958,10 +910,6 @@ ovfem_status ovfem_matvec(ovfem_solver* s, const double* u, double* Ku) {
     A.ku = Ku;
     A.src_nt = 0;
     A.rec_nt = 0;
-    if (s->precision == OVFEM_INT8 || s->precision == OVFEM_INT8_BF16) {
-      s->launch_exponents(s->geom, u, s->expo_tmp.p, 1);
-      A.exp_in = s->expo_tmp.p;
-    }
     launch_unit<MODE_MATVEC>(s->form(), A, nullptr, 0, s->stream);
   });
 }
@@ -988,7 +936,6 @@ ovfem_status ovfem_set_wavefield(ovfem_solver* s, const double* un, const double
     const size_t bytes = (size_t)s->n_shots * s->vec() * sizeof(double);
     OVFEM_HIP(hipMemcpyAsync(s->u[s->buf_cur(s->phase)].p, un, bytes, hipMemcpyDeviceToDevice, s->stream));
     OVFEM_HIP(hipMemcpyAsync(s->u[s->buf_prev(s->phase)].p, unm1, bytes, hipMemcpyDeviceToDevice, s->stream));
-    s->state_exponents();
     s->step = step;
     s->ckpt_valid = false;
     OVFEM_HIP(hipStreamSynchronize(s->stream));
@@ -1056,17 +1003,8 @@ ovfem_status ovfem_set_damping(ovfem_solver* s, double alpha, double beta) {
                                               std::to_string(s->dt_limit(beta)) + ")");
     if ((alpha != 0.0 || beta != 0.0) && !s->u[2].p) {
       DevBuf<double> u2;
-      DevBuf<int> e2;
-      try {
-        u2.alloc((size_t)s->n_shots * s->vec());
-        e2.alloc((size_t)s->n_shots * s->geom.n_wg);
-      } catch (...) {
-        u2.free();
-        e2.free();
-        throw;
-      }
+      u2.alloc((size_t)s->n_shots * s->vec());
       std::swap(s->u[2], u2);
-      std::swap(s->expo[2], e2);
     }
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     s->alpha = alpha;
@@ -1221,7 +1159,6 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
                                s->stream));
       OVFEM_HIP(hipMemcpyAsync(s->traces.p, keep_tr.p, s->traces.n * sizeof(double), hipMemcpyDeviceToDevice,
                                s->stream));
-      s->state_exponents();
       s->step = step0;
       OVFEM_HIP(hipStreamSynchronize(s->stream));
     } catch (...) {
@@ -1288,10 +1225,10 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
         }
       aptr[w + 1] = (int)anode.size();
     }
-    DevBuf<int> d_aptr, d_anode, d_acomp, d_arow, fexp, wexp;
+    DevBuf<int> d_aptr, d_anode, d_acomp, d_arow;
     DevBuf<double> seg, wbuf;
     auto free_all = [&] {
-      for (auto* b : {&d_aptr, &d_anode, &d_acomp, &d_arow, &fexp, &wexp}) b->free();
+      for (auto* b : {&d_aptr, &d_anode, &d_acomp, &d_arow}) b->free();
       seg.free();
       wbuf.free();
     };
@@ -1304,17 +1241,13 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       const bool damped = s->damped();
       const double bd = damped ? s->damp_b() : 0.0;
       wbuf.alloc(3 * vec);
-      fexp.alloc(2 * g.n_wg);
-      wexp.alloc(2 * g.n_wg);
       OVFEM_HIP(hipMemsetAsync(g_lam, 0, s->n_elem * sizeof(double), s->stream));
       OVFEM_HIP(hipMemsetAsync(g_mu, 0, s->n_elem * sizeof(double), s->stream));
       OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 3 * vec * sizeof(double), s->stream));
       // w[i1] = w^{m+1}, w[i2] = w^{m+2}; a step writes w^m over w^{m+2} (undamped) or
-      // into the third buffer (damped: the halo of w^{m+2} is read by neighbours); the
-      // exponent halves alternate, half we holding those of the next staged vector
+      // into the third buffer (damped: the halo of w^{m+2} is read by neighbours)
       double* w[3] = {wbuf.p, wbuf.p + vec, wbuf.p + 2 * vec};
-      int i1 = 0, i2 = 1, we = 0;
-      s->launch_exponents(g, w[i1], wexp.p, 1, damped ? w[i2] : nullptr, bd);
+      int i1 = 0, i2 = 1;
 
       KArgs F = s->shot_args(0, s->phase);  // forward recompute: forward sources, no recording
       F.rec_nt = 0;
@@ -1335,26 +1268,18 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           if (k == 0) return s->ckpt_u(sg, 0);
           return seg.p + (size_t)k * vec;
         };
-        int fe = 0;
-        s->launch_exponents(g, state(0), fexp.p, 1, damped ? state(-1) : nullptr, bd);
         for (int64_t t = s0; t < e0; ++t) {
           F.u = state(t - s0);
           F.uprev = state(t - s0 - 1);
           F.unext = state(t - s0 + 1);
-          F.exp_in = fexp.p + fe * g.n_wg;
-          F.exp_out = fexp.p + (fe ^ 1) * g.n_wg;
           launch_unit<MODE_STEP>(s->form(), F, nullptr, t, s->stream);
-          fe ^= 1;
         }
         for (int64_t m = e0; m > s0; --m) {
           const int inew = damped ? 3 - i1 - i2 : i2;
           B.u = w[i1];
           B.uprev = w[i2];
           B.unext = w[inew];
-          B.exp_in = wexp.p + we * g.n_wg;
-          B.exp_out = wexp.p + (we ^ 1) * g.n_wg;
           launch_unit<MODE_STEP>(s->form(), B, nullptr, m - 1, s->stream);
-          we ^= 1;
           i2 = i1;
           i1 = inew;
           const double* u1 = state(m - 1 - s0);

@@ -2,9 +2,10 @@
 the matrix cores), emulated exactly in Python integers.
 
 These pin the design the kernels rely on, not the oracle:
-  * q = floor(u 2^(QB - E)) with |q| <= 2^QB, QB = 8M - 2, is recovered exactly from the two
-    FP64 steps the kernels use (hd = floor(x 2^-32), lo = x - hd 2^32 converted with
-    saturation) for every |x| < 2^62;
+  * q = rint(u 2^(QB - S)) (round to nearest, ties to even) with |q| <= 2^QB, QB = 8M - 2,
+    is recovered exactly from the FP64 steps the kernels use (xr = rint(x), hd =
+    floor(xr 2^-32), lo = xr - hd 2^32 with 0 <= lo < 2^32: every step exact, every
+    conversion in range) for every |x| < 2^62;
   * the bytes of q + sum_j 128 * 256^j, less 128, are M balanced digits d_j in [-128, 127]
     with sum_j 256^j d_j = q, and the bytes above M are exactly 128 (digit 0);
   * the INT32 pair sums C = 256 A d_hi + A d_lo of the integer matrices stay below 2^31,
@@ -29,14 +30,16 @@ def _int_matrices():
 
 
 def _q_two_steps(x):
-    """The kernels' two FP64 steps for q = floor(x) (x a double, |x| < 2^62): hd = floor(x
-    2^-32), exact; lo = x - hd 2^32 rounded once (hd 2^32 is exact, so Python's double
-    subtraction is the kernels' fma), converted to uint32 with truncation and saturation
-    (a lo that rounds up to 2^32 saturates to 2^32 - 1, which is still floor(x))."""
-    hd = math.floor(x * 2.0 ** -32)
-    lo = x - hd * 2.0 ** 32
-    assert 0 <= lo <= 2 ** 32
-    return int(hd) * 2 ** 32 + min(int(lo), 2 ** 32 - 1)
+    """The kernels' FP64 steps for q = rint(x) (x a double, |x| < 2^62): xr = rint(x) in the
+    default rounding mode (Python's round() of a float also rounds ties to even); hd =
+    floor(xr 2^-32), exact; lo = xr - hd 2^32, an integer in [0, 2^32) and so exact (Python's
+    double subtraction is then the kernels' fma), converted to uint32 in range."""
+    xr = float(round(x))
+    assert xr == x or abs(xr - x) <= 0.5
+    hd = math.floor(xr * 2.0 ** -32)
+    lo = xr - hd * 2.0 ** 32
+    assert 0 <= lo < 2 ** 32 and lo == int(lo)
+    return int(hd) * 2 ** 32 + int(lo)
 
 
 def _digits(q, M):
@@ -50,13 +53,18 @@ def _digits(q, M):
 def test_split_and_reconstruct_are_exact(M):
     QB = 8 * M - 2
     rng = random.Random(M)
-    cases = [0.0, 0.5, -0.5, 1 - 2 ** -53, -(1 - 2 ** -53), 2 ** -60, -(2 ** -60)]
+    cases = [0.0, 0.5, -0.5, 1 - 2 ** -53, -(1 - 2 ** -53), 2 ** -60, -(2 ** -60), -(2.0 ** -300)]
+    cases += [math.ldexp(k + 0.5, -QB) for k in (-3, -2, -1, 0, 1, 2)]  # ties
+    if QB <= 51:  # values that round to q = +-2^QB, the largest magnitude
+        cases += [math.ldexp(2.0 ** QB - 0.25, -QB), -math.ldexp(2.0 ** QB - 0.25, -QB)]
     cases += [rng.uniform(-1, 1) * 2.0 ** -rng.randrange(0, 70) for _ in range(4000)]
-    for u in cases:  # u already scaled by 2^-E: |u| < 1 (the tile exponent makes it so)
+    for u in cases:  # u already scaled by 2^-S: |u| < 1 (the staging exponent makes it so)
         x = math.ldexp(u, QB)
-        q = _q_two_steps(x) if M > 4 else math.floor(x)
-        assert q == math.floor(Fraction(u) * 2 ** QB)
-        assert abs(q) < 2 ** QB or q == -(2 ** QB)
+        q = _q_two_steps(x) if M > 4 else int(round(x))
+        assert q == round(Fraction(u) * 2 ** QB)
+        assert abs(q) <= 2 ** QB
+        if abs(u) < 2.0 ** (-QB - 1):
+            assert q == 0  # tiny values round to zero, whatever their sign
         d, rest = _digits(q, M)
         assert all(-128 <= v <= 127 for v in d)
         assert all(v == 0 for v in rest)
@@ -84,7 +92,7 @@ def test_horner_over_pair_sums_is_the_integer_product(M):
     QB = 8 * M - 2
     for trial in range(30):
         u = rng.uniform(-1, 1, 24) * 2.0 ** -rng.integers(0, 20, 24)
-        q = [math.floor(Fraction(float(v)) * 2 ** QB) for v in u]
+        q = [round(Fraction(float(v)) * 2 ** QB) for v in u]
         digits = [_digits(v, M)[0] for v in q]
         for A in (AL, AM):
             for row in A:
