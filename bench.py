@@ -21,6 +21,9 @@ Other workloads (parity cases, one JSON line each, not the headline):
   --workload c3-shots    64 shots on 128 x 128 x 64 in one launch per step
   --workload c3-uneven   16 layered domains of uneven size, one batched launch per step
   --workload c5-slab     512 x 512 x 32 of the c5 recipe: one GPU's share of c5 split 8 ways
+  --workload c4-adjoint  96^3 misfit gradient: forward run with checkpoints every 50 steps, then
+                         the discrete adjoint (recompute + backward step + gradient terms) per path,
+                         gradients checked against the stored full-length oracle adjoint
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload NAME]
 (--steps defaults to the workload's run length: 4000 for c5, 2000 for c2, 1000 for c3)
@@ -46,10 +49,11 @@ FP64_FLOP_PER_ELEMENT = 2 * 2 * 24 * 24   # AL u and AM u in FP64
 
 
 # run length of each workload: the untimed parity leg compares the paths' traces over it
-FULL_STEPS = {"c2": 2000, "c3-shots": 1000, "c3-uneven": 1000, "c5": 4000, "c5-slab": 4000}
+FULL_STEPS = {"c2": 2000, "c3-shots": 1000, "c3-uneven": 1000, "c5": 4000, "c5-slab": 4000, "c4-adjoint": 1000}
 
 KERNEL_SOURCES = ["paper_2404_13683_amd/csrc/kernels.hpp", "paper_2404_13683_amd/csrc/refmat.hpp"]
 EQUAL_ACCURACY = os.path.join(ROOT, "tests", "golden", "equal_dispersion_accuracy.json")
+C4_ORACLE = os.path.join(ROOT, "tests", "golden", "fullsize_c4.json")
 # rocprofv3 counter summaries of the stepper kernels, per workload
 COUNTERS_FILES = {
     "c2": os.path.join(ROOT, "profiles", "layer_kernel_counters_layered_256x256x128.txt"),
@@ -310,6 +314,68 @@ def cpu_sample(name, wls):
                   "(%d free DOF)" % (k0, k0 + kz - 1, slab.free_dof()))
 
 
+def adjoint_bench(args):
+    """The 96^3 misfit gradient on each path: the forward run from rest with checkpoints
+    every 50 steps, then the discrete adjoint, each timed with HIP events on the solver's
+    stream; gradients at the stored voxels against the oracle's full-length adjoint."""
+    import torch
+
+    from paper_2404_13683_amd import workloads
+    from paper_2404_13683_amd.ovfem import Solver
+    fx = json.load(open(C4_ORACLE))
+    true, start = workloads.adjoint_c4()
+    nt, every = start.nt, fx["ckpt_every"]
+    s = Solver.from_workload(true, precision="fp64")
+    s.step(nt)
+    d_obs = s.get_traces().clone()
+    s.close()
+    vox = tuple(np.array(fx["voxels"]).T)
+    stream = torch.cuda.current_stream()
+    free_dof = start.free_dof()
+    out = {}
+    for p in args.paths.split(","):
+        s = Solver.from_workload(start, precision=p)
+        if not args.no_autotune:
+            s.autotune(steps=20)
+        s.set_checkpointing(every, nt)
+        s.reset()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s.step(nt)
+        e1.record(stream)
+        res = (s.get_traces() - d_obs).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g_lam, g_mu = s.adjoint(res)  # returns after its stream has drained
+        e2.record(stream)
+        torch.cuda.synchronize()
+        adj_s = time.perf_counter() - t0
+        fwd_ms = e0.elapsed_time(e1) / nt
+        J = 0.5 * float(torch.sum(res * res))
+        gl, gm = g_lam.cpu().numpy(), g_mu.cpu().numpy()
+        rel = lambda a, b: float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+        out[p] = {"forward_ms_per_step": fwd_ms, "adjoint_ms_per_step": adj_s * 1e3 / nt,
+                  "adjoint_value": free_dof * nt / adj_s, "tuning": s.get_tuning(),
+                  "vs_oracle": {"J": abs(J - fx["J"]) / fx["J"], "g_lam": rel(gl[vox], fx["g_lam"]),
+                                "g_mu": rel(gm[vox], fx["g_mu"]), "voxels": len(vox[0])}}
+        print("[bench] c4-adjoint %s: forward %.4f ms/step, adjoint %.4f ms/step, vs oracle %s"
+              % (p, fwd_ms, adj_s * 1e3 / nt, out[p]["vs_oracle"]), file=sys.stderr, flush=True)
+        s.close()
+    head = "int8" if "int8" in out else list(out)[0]
+    line = {
+        "metric": "adjoint gradient DOF-updates/s (recompute + backward step + gradient terms per step)",
+        "value": out[head]["adjoint_value"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": nt, "warmup": 0,
+        "ms_per_step": out[head]["adjoint_ms_per_step"], "higher_is_better": True, "vs_baseline": None,
+        "dtype": "int8-digits(i8-mfma,int32-acc,exact)+f64" if head == "int8" else "f64", "data": "synthetic",
+        "config": {"workload": "adjoint 96^3 (%d free DOF), h=5 m, 1000 steps, checkpoints every %d, 32 surface "
+                              "receivers; start model homogeneous against a +-15 %% smooth true model"
+                              % (free_dof, every), "path": head},
+        "paths": out,
+    }
+    print(json.dumps(line))
+
+
 def make_workload(name, nt):
     """(list of workloads, description, batched?) for a workload name."""
     from paper_2404_13683_amd import workloads
@@ -347,7 +413,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--paths", default="fp64,int8,fp64-sf")
-    ap.add_argument("--workload", default="c5", choices=["c5", "c2", "c3-shots", "c3-uneven", "c5-slab"])
+    ap.add_argument("--workload", default="c5",
+                    choices=["c5", "c2", "c3-shots", "c3-uneven", "c5-slab", "c4-adjoint"])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--chunk-planes", type=int, default=0, help="fixed z-chunk depth instead of autotuning")
     ap.add_argument("--no-equal-accuracy", action="store_true", help="skip the trilinear comparison")
@@ -365,6 +432,11 @@ def main():
               "model or its shots across GPUs" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c4-adjoint":
+        import torch
+        torch.cuda.set_device(0)
+        adjoint_bench(args)
+        return
     full = FULL_STEPS[args.workload]
     if args.steps is None:
         args.steps = full

@@ -963,12 +963,48 @@ static __global__ void ovfem_advance_step_kernel(long long* step_base, long long
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
 }
 
+// The two energies w^T K_lam u and w^T K_mu u of one element (h = 1) in the
+// sum-factorised form of sf_component: with W, Wh the Walsh coefficients of u and w
+// (sf_transform) and f_b = (1/16) q^|b| (q = 3/4 OVFEM, 1/3 trilinear),
+//     w^T K_lam u = sum_b f_b tr_b(u) tr_b(w),
+//     w^T K_mu u  = sum_b f_b sum_{j not in b} sum_c Wh_c[b+{j}] (W_c[b+{j}] + [c not in b] W_j[b+{c}]),
+// since w^T y = sum_{c,S} Wh_c[S] V_c[S] for y_{alpha,c} = sum_S chi_S(alpha) V_c[S].
+template <int ELEM>
+__device__ inline void sf_energies(const double W[3][8], const double tr[7], const double Wh[3][8],
+                                   const double trh[7], double& el, double& em) {
+  constexpr double q = ELEM == 1 ? 1.0 / 3.0 : 0.75;
+  const double f[3] = {1.0 / 16.0, q / 16.0, q * q / 16.0};
+  el = 0.0;
+  em = 0.0;
+#pragma unroll
+  for (int ib = 0; ib < 7; ++ib) {
+    const int b = kSfB[ib];
+    const int nb = (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1);
+    double sm = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if ((b >> j) & 1) continue;
+      const int S = b | (1 << j);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double g = W[c][S];
+        if (!((b >> c) & 1)) g += W[j][b | (1 << c)];
+        sm = fma(Wh[c][S], g, sm);
+      }
+    }
+    el = fma(f[nb] * tr[ib], trh[ib], el);
+    em = fma(f[nb], sm, em);
+  }
+}
+
 // Per-element gradient terms of the discrete adjoint: for every solid element e,
 //     g_lam[e] -= h w_e^T K_lam u_e,   g_mu[e] -= h w_e^T K_mu u_e,
 // with u = u^{m-1} (with Rayleigh damping the staged (1+b) u^{m-1} - b u^{m-2}, b = beta/dt)
 // and w = w^m (the derivative of w^T K u with respect to lam_e, mu_e,
-// from K_e = h (lam_e K_lam + mu_e K_mu)).  One thread per element; each element's
-// sums are private, so the accumulation order is fixed.  ELEM: 0 OVFEM, 1 trilinear.
+// from K_e = h (lam_e K_lam + mu_e K_mu)).  The energies are formed sum-factorised
+// (sf_energies: about 300 flops per element instead of the 2304 of two dense 24 x 24
+// products).  One thread per element; each element's sums are private, so the
+// accumulation order is fixed.  ELEM: 0 OVFEM, 1 trilinear.
 template <int ELEM>
 __global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, const double* mat,
                                                                const double* u, const double* u2, double b,
@@ -991,20 +1027,13 @@ __global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, 
       we[3 * alpha + c] = w[3 * n + c];
     }
   }
-  double gl = 0.0, gm = 0.0;
-#pragma unroll
-  for (int r = 0; r < 24; ++r) {
-    double sl = 0.0, sm = 0.0;
-#pragma unroll
-    for (int q = 0; q < 24; ++q) {
-      sl = fma((double)elem_al<ELEM>(r, q), ue[q], sl);
-      sm = fma((double)elem_am<ELEM>(r, q), ue[q], sm);
-    }
-    gl = fma(we[r], sl, gl);
-    gm = fma(we[r], sm, gm);
-  }
-  g_lam[e] -= h / kElemScaleLam[ELEM] * gl;
-  g_mu[e] -= h / kElemScaleMu[ELEM] * gm;
+  double Wu[3][8], tru[7], Ww[3][8], trw[7];
+  sf_transform(ue, Wu, tru);
+  sf_transform(we, Ww, trw);
+  double gl, gm;
+  sf_energies<ELEM>(Wu, tru, Ww, trw, gl, gm);
+  g_lam[e] -= h * gl;
+  g_mu[e] -= h * gm;
 }
 
 }  // namespace ovfem

@@ -631,16 +631,79 @@ struct ovfem_solver {
   }
 };
 
+// Argument tables of a batched launch.  Table q holds every unit's arguments for the
+// batch steps B with B % kBatchTables == q (a member's buffer phase cycles with period 2,
+// or 3 when damped), and each unit's step offset: its member's step minus the batch's.
+// While the members advance only through the batch the tables stay the same from one
+// call to the next, so they are uploaded again only when a member was changed or stepped
+// alone.
+constexpr int kBatchTables = 6;
+
 struct ovfem_batch {
   std::vector<ovfem_solver*> members;
   hipStream_t stream = nullptr;
   int persist_groups = 0;
-  DevBuf<KArgs> units;  // [relative step mod 6][unit]
-  DevBuf<int> begin;    // [unit + 1]
+  long long steps = 0;         // batch steps taken (B of the next step)
+  std::vector<KArgs> t_host;   // the tables as last uploaded, [B mod 6][unit]
+  std::vector<int> begin_host; // [unit + 1]: first work item of each unit
+  DevBuf<KArgs> units;
+  DevBuf<int> begin;
   ~ovfem_batch() {
     (void)hipStreamSynchronize(stream);
     units.free();
     begin.free();
+  }
+
+  // validate the members for a batched launch; returns the work-item count
+  double check_members() const {
+    double items = 0;
+    for (auto* m : members) {
+      require(m->form_code() == members[0]->form_code(), "ovfem_batch_step: members differ in precision or stages",
+              OVFEM_ESTATE);
+      require(m->damped() == members[0]->damped(),
+              "ovfem_batch_step: damped and undamped members cannot share a batch", OVFEM_ESTATE);
+      m->check_device();
+      items += (double)m->n_shots * m->geom.n_wg;
+    }
+    require(items < 2147483647.0, "ovfem_batch_step: too many work items");
+    return items;
+  }
+
+  // the tables for batch steps from `steps` on (t: [B mod 6][unit], begin: [unit + 1])
+  void tables(std::vector<KArgs>& t, std::vector<int>& bg) const {
+    bg.assign(1, 0);
+    for (auto* m : members)
+      for (int s = 0; s < m->n_shots; ++s) bg.push_back(bg.back() + m->geom.n_wg);
+    const size_t n_units = bg.size() - 1;
+    t.assign((size_t)kBatchTables * n_units, KArgs{});
+    const int q0 = (int)(steps % kBatchTables);
+    size_t v = 0;
+    for (auto* m : members)
+      for (int s = 0; s < m->n_shots; ++s, ++v)
+        for (int q = 0; q < kBatchTables; ++q) {
+          int ph = m->phase;  // phase at the next batch step; then advance to a step with B % 6 == q
+          for (int i = 0; i < (q - q0 + kBatchTables) % kBatchTables; ++i) ph = m->buf_next(ph);
+          KArgs A = m->shot_args(s, ph);
+          A.step = m->step - steps;
+          std::memcpy(&t[(size_t)q * n_units + v], &A, sizeof(KArgs));  // padding stays zero
+        }
+  }
+
+  // enqueue n steps reading the tables at `units` / `bg`, then advance the members
+  void launch(const KArgs* units_d, const int* begin_d, int64_t n) {
+    const Form form = members[0]->form();
+    const int n_units = (int)begin_host.size() - 1, total = begin_host.back();
+    for (int64_t i = 0; i < n; ++i) {
+      const long long B = steps + i;
+      launch_units(form, units_d + (size_t)(B % kBatchTables) * n_units, begin_d, n_units, total, persist_groups,
+                   nullptr, B, stream);
+    }
+    for (auto* m : members) {
+      for (int64_t i = 0; i < n % m->n_phase(); ++i) m->phase = m->buf_next(m->phase);
+      m->step += n;
+      m->ckpt_valid = false;
+    }
+    steps += n;
   }
 };
 
@@ -1337,47 +1400,29 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
   return guarded([&] {
     require(b != nullptr, "ovfem_batch_step: batch is NULL");
     require(n >= 0, "ovfem_batch_step: n < 0");
-    const Form form = b->members[0]->form();
-    double items = 0;
-    for (auto* m : b->members) {
-      require(m->form_code() == b->members[0]->form_code(), "ovfem_batch_step: members differ in precision or stages",
-              OVFEM_ESTATE);
-      require(m->damped() == form.damp, "ovfem_batch_step: damped and undamped members cannot share a batch",
-              OVFEM_ESTATE);
-      m->check_device();
-      items += (double)m->n_shots * m->geom.n_wg;
-    }
-    require(items < 2147483647.0, "ovfem_batch_step: too many work items");
+    b->check_members();
     if (n == 0) return;
     for (auto* m : b->members) m->prepare_steps();
-    // one unit per shot of each member; table q holds the arguments for relative steps
-    // i with i % 6 == q (a member's phase cycles with period 2, or 3 when damped)
-    constexpr int NQ = 6;
     std::vector<KArgs> t;
-    std::vector<int> begin(1, 0);
-    for (int q = 0; q < NQ; ++q)
-      for (auto* m : b->members) {
-        int ph = m->phase;
-        for (int i = 0; i < q; ++i) ph = m->buf_next(ph);
-        for (int s = 0; s < m->n_shots; ++s) {
-          KArgs A = m->shot_args(s, ph);
-          A.step = m->step;
-          t.push_back(A);
-          if (q == 0) begin.push_back(begin.back() + m->geom.n_wg);
-        }
+    std::vector<int> bg;
+    b->tables(t, bg);
+    const bool same = t.size() == b->t_host.size() && bg == b->begin_host &&
+                      std::memcmp(t.data(), b->t_host.data(), t.size() * sizeof(KArgs)) == 0;
+    if (!same) {
+      if (b->units.n < t.size() || b->begin.n < bg.size()) {
+        OVFEM_HIP(hipStreamSynchronize(b->stream));  // earlier launches may still read the old tables
+        b->units.alloc(t.size());
+        b->begin.alloc(bg.size());
       }
-    const int n_units = (int)begin.size() - 1, total = begin.back();
-    OVFEM_HIP(hipStreamSynchronize(b->stream));  // earlier batch launches may read the old tables
-    upload(b->units, t, b->stream);
-    upload(b->begin, begin, b->stream);
-    for (int64_t i = 0; i < n; ++i)
-      launch_units(form, b->units.p + (size_t)(i % NQ) * n_units, b->begin.p, n_units, total, b->persist_groups,
-                   nullptr, i, b->stream);
-    for (auto* m : b->members) {
-      for (int64_t i = 0; i < n % NQ; ++i) m->phase = m->buf_next(m->phase);
-      m->step += n;
-      m->ckpt_valid = false;
+      b->t_host.swap(t);
+      b->begin_host.swap(bg);
+      // stream-ordered after the launches that read the previous contents
+      OVFEM_HIP(hipMemcpyAsync(b->units.p, b->t_host.data(), b->t_host.size() * sizeof(KArgs),
+                               hipMemcpyHostToDevice, b->stream));
+      OVFEM_HIP(hipMemcpyAsync(b->begin.p, b->begin_host.data(), b->begin_host.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
     }
+    b->launch(b->units.p, b->begin.p, n);
   });
 }
 

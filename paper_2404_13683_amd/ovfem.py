@@ -122,6 +122,12 @@ class Solver:
         self.n_rec = 0
         self.rec_nt = 0
         self.dt = None
+        # bumped by every call that changes the run the checkpoints and traces belong to
+        # (model, problem, path, wavefield, stepping); the autograd wrapper compares it
+        self.generation = 0
+
+    def _touch(self):
+        self.generation += 1
 
     def close(self):
         if self._h:
@@ -142,6 +148,7 @@ class Solver:
 
     # --- configuration (host arrays)
     def set_precision(self, precision):
+        self._touch()
         _check(_LIB.ovfem_set_precision(self._h, PRECISIONS[precision]))
 
     def set_model(self, lam, mu, rho, solid=None):
@@ -157,9 +164,11 @@ class Solver:
             sa, sp = _host(solid, np.uint8)
             if sa.size != n:
                 raise ValueError("solid must have nx*ny*nz entries")
+        self._touch()
         _check(_LIB.ovfem_set_model(self._h, lp, mp, rp, sp))
 
     def set_fixed_nodes(self, fixed):
+        self._touch()
         if fixed is None:
             _check(_LIB.ovfem_set_fixed_nodes(self._h, None))
             return
@@ -169,6 +178,7 @@ class Solver:
         _check(_LIB.ovfem_set_fixed_nodes(self._h, fp))
 
     def set_dt(self, dt):
+        self._touch()
         _check(_LIB.ovfem_set_dt(self._h, float(dt)))
         self.dt = float(dt)
 
@@ -183,10 +193,12 @@ class Solver:
         sp = None
         if shot is not None:
             sa, sp = _host(shot, np.int32)
+        self._touch()
         _check(_LIB.ovfem_set_sources(self._h, n, np_, cp, sp, wp, nt))
 
     def set_receivers(self, node, nt_max):
         na, np_ = _host(node, np.int64)
+        self._touch()
         _check(_LIB.ovfem_set_receivers(self._h, int(na.size), np_, int(nt_max)))
         self.n_rec, self.rec_nt = int(na.size), int(nt_max)
 
@@ -219,9 +231,11 @@ class Solver:
             cur.wait_stream(self.stream)
 
     def reset(self):
+        self._touch()
         _check(_LIB.ovfem_reset(self._h))
 
     def step(self, n=1):
+        self._touch()
         _check(_LIB.ovfem_step(self._h, int(n)))
 
     def synchronize(self):
@@ -258,6 +272,7 @@ class Solver:
     def set_wavefield(self, un, unm1, step=0):
         n = self.n_shots * 3 * self.n_nodes
         self._order_in()
+        self._touch()
         _check(_LIB.ovfem_set_wavefield(self._h, _dev_f64(un, n, "un", self.device),
                                         _dev_f64(unm1, n, "unm1", self.device), int(step)))
 
@@ -272,6 +287,7 @@ class Solver:
         return out.view(self.n_shots, self.n_rec, 3, self.rec_nt)
 
     def set_checkpointing(self, every, max_steps):
+        self._touch()
         _check(_LIB.ovfem_set_checkpointing(self._h, int(every), int(max_steps)))
 
     def adjoint(self, residual):
@@ -296,14 +312,17 @@ class Solver:
 
     # --- element type (before the model)
     def set_element(self, element):
+        self._touch()
         _check(_LIB.ovfem_set_element(self._h, ELEMENTS[element]))
 
     # --- Rayleigh damping C = alpha M + beta K
     def set_damping(self, alpha, beta):
+        self._touch()
         _check(_LIB.ovfem_set_damping(self._h, float(alpha), float(beta)))
 
     # --- digit stages of the INT8 form
     def set_stages(self, stages):
+        self._touch()
         _check(_LIB.ovfem_set_stages(self._h, int(stages)))
 
     def get_stages(self):
@@ -313,6 +332,7 @@ class Solver:
 
     # --- launch configuration
     def set_tuning(self, chunk_planes=16, persistent_groups=0, graph_steps=0):
+        self._touch()
         _check(_LIB.ovfem_set_tuning(self._h, int(chunk_planes), int(persistent_groups), int(graph_steps)))
 
     def get_tuning(self):
@@ -323,6 +343,7 @@ class Solver:
     def autotune(self, steps=20):
         """Pick the fastest launch configuration; returns its ms per step."""
         ms = _f64()
+        self._touch()
         _check(_LIB.ovfem_autotune(self._h, int(steps), ctypes.byref(ms)))
         return ms.value
 
@@ -340,6 +361,8 @@ class Batch:
         _check(_LIB.ovfem_batch_set_tuning(self._h, int(persistent_groups)))
 
     def step(self, n=1):
+        for m in self.members:
+            m._touch()
         _check(_LIB.ovfem_batch_step(self._h, int(n)))
 
     def close(self):

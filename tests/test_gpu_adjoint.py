@@ -132,3 +132,31 @@ def test_autograd_function_gives_the_adjoint_gradient():
     _, gl_ref, gm_ref = oasm.adjoint_gradient(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node, d_obs)
     assert _rel(lam.grad.cpu().numpy(), gl_ref) <= 1e-9
     assert _rel(mu.grad.cpu().numpy(), gm_ref) <= 1e-9
+
+
+def test_autograd_backward_refuses_a_solver_used_for_another_run():
+    import torch
+
+    from paper_2404_13683_amd import autograd
+    from paper_2404_13683_amd.ovfem import Solver
+    w, d_obs = _case(nx=8, ny=7, nz=6, nt=30, seed=5)
+    s = Solver.from_workload(w, precision="fp64")
+    obs = torch.from_numpy(d_obs).cuda()
+    lam = torch.from_numpy(w.lam).cuda().requires_grad_(True)
+    mu = torch.from_numpy(w.mu).cuda().requires_grad_(True)
+    J1 = 0.5 * ((autograd.traces(s, lam, mu, w.rho, nt=w.nt, ckpt_every=10)[0] - obs) ** 2).sum()
+    # a second model evaluated on the same solver before the first backward
+    lam2 = (lam.detach() * 1.01).requires_grad_(True)
+    J2 = 0.5 * ((autograd.traces(s, lam2, mu, w.rho, nt=w.nt, ckpt_every=10)[0] - obs) ** 2).sum()
+    with pytest.raises(RuntimeError, match="after this forward run"):
+        J1.backward()
+    J2.backward()  # the latest run still differentiates
+    assert torch.isfinite(lam2.grad).all() and lam2.grad.abs().max() > 0
+    # in-place edits of a saved material after the forward are caught by autograd
+    lam3 = torch.from_numpy(w.lam).cuda().requires_grad_(True)
+    mu3 = torch.from_numpy(w.mu).cuda()
+    J3 = 0.5 * ((autograd.traces(s, lam3, mu3, w.rho, nt=w.nt, ckpt_every=10)[0] - obs) ** 2).sum()
+    mu3.mul_(1.01)
+    with pytest.raises(RuntimeError):
+        J3.backward()
+    s.close()
