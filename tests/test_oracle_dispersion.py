@@ -78,3 +78,22 @@ def test_equal_dispersion_accuracy_fixture():
     assert rows[10]["ppw_trilinear"] > 10 and rows[10]["cost_factor"] > 1
     assert rows[5]["rms_phase_error"] / rows[10]["rms_phase_error"] == pytest.approx(4.0, rel=0.1)
     assert rows[10]["rms_phase_error"] / rows[20]["rms_phase_error"] == pytest.approx(4.0, rel=0.02)
+
+
+@pytest.mark.parametrize("which,ppw,s_ratio,p_ratio", [
+    ("ovfem", 10, 0.99850, 0.98035),
+    ("trilinear", 10, 0.97833, 0.97025),
+    ("ovfem", 5, 0.99253, None),
+    ("trilinear", 5, 0.91639, None),
+])
+def test_diagonal_phase_velocities_match_an_independent_bloch_computation(which, ppw, s_ratio, p_ratio):
+    """Semi-discrete phase velocities along (1, 1, 1) at ppw grid points per wavelength
+    (Vp = 2 Vs), against values of a separate computation of the plane-wave symbol from the
+    exact element integrals (five digits): a transposed block, a wrong phase sign or a wrong
+    element weight moves them in the third digit or earlier."""
+    h = 1.0
+    K = _ovfem(h) if which == "ovfem" else el.trilinear_stiffness(LAM, MU, h)
+    c = dsp.phase_velocities(K, RHO, h, (1, 1, 1), 2 * np.pi / ppw)
+    assert abs(c[0] / VS - s_ratio) < 6e-6 and abs(c[1] / VS - s_ratio) < 6e-6
+    if p_ratio is not None:
+        assert abs(c[2] / VP - p_ratio) < 6e-6

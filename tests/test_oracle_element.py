@@ -217,3 +217,14 @@ def test_trilinear_constant_strain_energy():
     energy = 0.5 * u @ (h * (lam * Kl + mu * Km)) @ u
     cont = 0.5 * h ** 3 * (lam * np.trace(E) ** 2 + 2 * mu * np.sum(E * E))
     assert abs(energy - cont) <= 1e-13 * cont
+
+
+def test_first_rows_of_the_integer_matrices():
+    """Row 0 (corner 0, x component) of 256 K_lam and 128 K_mu, as integers: the values of a
+    separate derivation of the element integrals with the same node numbering."""
+    Kl, Km = el.ovfem_reference()
+    row_l = [49, 28, 28, -49, 28, 28, 7, -28, 4, -7, -28, 4, 7, 4, -28, -7, 4, -28, 1, -4, -4, -1, -4, -4]
+    row_m = [98, 14, 14, -42, -14, -14, -14, 14, 2, -10, -14, -2, -14, 2, 14, -10, -2, -14, -6, 2, 2, -2, -2, -2]
+    assert np.array_equal(256 * Kl[0], np.array(row_l, dtype=float))
+    assert np.array_equal(128 * Km[0], np.array(row_m, dtype=float))
+    assert np.abs(256 * Kl[0]).sum() == 384
