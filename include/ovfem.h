@@ -254,9 +254,10 @@ ovfem_status ovfem_get_tuning(ovfem_solver* s, int32_t* chunk_planes, int32_t* p
                               int32_t* graph_steps);
 
 /* Autotuner: times `steps` (2..100000) plain-launch steps of the solver's own model,
- * sources and precision for each candidate chunk depth (8, 12, 16, 24, 32 planes) and,
- * for n_shots > 1, grid caps of 0, 2 and 4 work-groups per compute unit, keeps the
- * fastest, then times graph_steps 0 and 64 at that setting and keeps the faster.  The wavefield pair, traces and step counter are
+ * sources and precision for each candidate chunk depth (8, 12, 16, 24, 32, 48, 64, 96
+ * planes, each evened out over the chunks it gives) and, for n_shots > 1, grid caps of
+ * 0, 2 and 4 work-groups per compute unit, keeps the fastest, then times graph_steps 0
+ * and 64 at that setting and keeps the faster.  The wavefield pair, traces and step counter are
  * restored afterwards; a checkpointed forward run is invalidated.  best_ms_per_step
  * (HOST, nullable) receives the best time per step in milliseconds.  Synchronises the
  * stream.  ESTATE without model and dt. */

@@ -473,10 +473,12 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     for (int i = 0; i < 3; ++i) a_frag8[i] = (long)A.alane8[i * 64 + lane];
   }
 
-  // staged nodes: main node (ta+1, tb+1); the first 33 lanes of the last wave stage
-  // one more (the row q = 0 and the column p = 0 of the plane)
-  const int xi = t - (NTHR - 64);
-  const bool has_extra = xi >= 0 && xi < NEXTRA;
+  // staged nodes: main node (ta+1, tb+1); 33 threads stage one more (extra node xi of
+  // the row q = 0 and the column p = 0 of the plane), dealt round-robin over the four
+  // waves (9, 8, 8, 8), so that no wave, and no SIMD, does a second node's loads and
+  // digit split alone while the others wait at the layer's barrier
+  const int xi = lane < (NEXTRA + 3) / 4 ? 4 * lane + wave : NEXTRA;
+  const bool has_extra = xi < NEXTRA;
   const int mp = ta + 1, mq = tb + 1;
   const int xp = xi < PN ? xi : 0, xq = xi < PN ? 0 : xi - (PN - 1);
   const NodeRef main_ref = node_ref(g, x0 - 1 + mp, y0 - 1 + mq);

@@ -689,10 +689,11 @@ struct ovfem_batch {
         }
   }
 
-  // enqueue n steps reading the tables at `units` / `bg`, then advance the members
-  void launch(const KArgs* units_d, const int* begin_d, int64_t n) {
+  // enqueue n steps reading the device tables units_d / begin_d (bg: the host copy of
+  // begin_d), then advance the members
+  void launch(const KArgs* units_d, const int* begin_d, const std::vector<int>& bg, int64_t n) {
     const Form form = members[0]->form();
-    const int n_units = (int)begin_host.size() - 1, total = begin_host.back();
+    const int n_units = (int)bg.size() - 1, total = bg.back();
     for (int64_t i = 0; i < n; ++i) {
       const long long B = steps + i;
       launch_units(form, units_d + (size_t)(B % kBatchTables) * n_units, begin_d, n_units, total, persist_groups,
@@ -1159,7 +1160,7 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       OVFEM_HIP(hipGetLastError());
       fill_random_kernel<<<fill_blocks, 256, 0, s->stream>>>(s->u[s->buf_prev(s->phase)].p, nv, 2, 1e-6);
       OVFEM_HIP(hipGetLastError());
-      std::vector<int> plane_opts = {8, 12, 16, 24, 32};
+      std::vector<int> plane_opts = {8, 12, 16, 24, 32, 48, 64, 96};
       std::vector<int> persist_opts = {0};
       if (s->n_shots > 1) {
         hipDeviceProp_t prop;
@@ -1422,7 +1423,7 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
       OVFEM_HIP(hipMemcpyAsync(b->begin.p, b->begin_host.data(), b->begin_host.size() * sizeof(int),
                                hipMemcpyHostToDevice, b->stream));
     }
-    b->launch(b->units.p, b->begin.p, n);
+    b->launch(b->units.p, b->begin.p, b->begin_host, n);
   });
 }
 
