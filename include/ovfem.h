@@ -77,6 +77,7 @@ typedef int32_t ovfem_status;
 /* limits */
 #define OVFEM_MAX_SHOTS 4096 /* shots per solver */
 #define OVFEM_MAX_BATCH 4096 /* solvers per batch */
+#define OVFEM_NOALLOC_SCRATCH_BYTES (1 << 20) /* fixed device array of ovfem_batch_step_noalloc */
 
 typedef struct ovfem_solver ovfem_solver;
 typedef struct ovfem_batch ovfem_batch;
@@ -281,6 +282,20 @@ ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups);
  * own step counter.  Members must share one precision (and stage count) and have model and dt set
  * (ESTATE otherwise).  Invalidates the members' checkpointed forward runs. */
 ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ovfem_batch_step with the batch's
+ * argument tables in a fixed array of OVFEM_NOALLOC_SCRATCH_BYTES bytes of device memory
+ * that the library holds on every device it runs on until the process ends, instead of
+ * device buffers it allocates.  It calls no hipMalloc or hipFree.  Results are those of
+ * ovfem_batch_step (bitwise: the same kernels on the same tables); asynchronous likewise.
+ * The tables take 6 * 240 + 4 bytes per unit (a unit is one shot of one member) plus 4:
+ * EINVAL beyond OVFEM_NOALLOC_SCRATCH_BYTES (726 units).  ESTATE unless every member has
+ * model and dt set and has stepped since its model, fixed nodes, dt or damping last
+ * changed (ovfem_step(member, 0) suffices: it builds the member's dt^2/m table).
+ * Every call on one device writes the same array: calls on one stream are ordered, calls
+ * on different streams of one device that overlap in time race. */
+ovfem_status ovfem_batch_step_noalloc(ovfem_batch* b, int64_t n);
 
 /* Blow-up check: *finite = 1 if every value of the current wavefield pair (u^n, u^{n-1})
  * of every shot is finite, 0 if any is NaN or infinite.  With dt inside the bound that

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <exception>
 #include <limits>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -648,6 +649,8 @@ struct ovfem_batch {
   std::vector<int> begin_host; // [unit + 1]: first work item of each unit
   DevBuf<KArgs> units;
   DevBuf<int> begin;
+  std::vector<KArgs> t_fixed;  // host side of ovfem_batch_step_noalloc's tables (capacity kept)
+  std::vector<int> begin_fixed;
   ~ovfem_batch() {
     (void)hipStreamSynchronize(stream);
     units.free();
@@ -707,6 +710,32 @@ struct ovfem_batch {
     steps += n;
   }
 };
+
+// Device memory of ovfem_batch_step_noalloc: a fixed array in the code object, one copy
+// per device, held until the process ends.  Host code must not pass its name to a kernel
+// or a copy (it is a host-side stand-in); scratch_address() gives each device's address.
+static __device__ __align__(256) unsigned char scratch[OVFEM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mutex;
+std::vector<unsigned char*> g_scratch_address;  // [device]
+
+// The current device's address of `scratch`, looked up once per device with that device
+// current.
+unsigned char* scratch_address() {
+  int device = -1;
+  OVFEM_HIP(hipGetDevice(&device));
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if ((int)g_scratch_address.size() <= device) g_scratch_address.resize(device + 1, nullptr);
+  if (!g_scratch_address[device]) {
+    void* p = nullptr;
+    OVFEM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    require(p != nullptr, "ovfem_batch_step_noalloc: no device address for the scratch array", OVFEM_EDEVICE);
+    g_scratch_address[device] = static_cast<unsigned char*>(p);
+  }
+  return g_scratch_address[device];
+}
+}  // namespace
 
 extern "C" {
 
@@ -1424,6 +1453,35 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
                                hipMemcpyHostToDevice, b->stream));
     }
     b->launch(b->units.p, b->begin.p, b->begin_host, n);
+  });
+}
+
+ovfem_status ovfem_batch_step_noalloc(ovfem_batch* b, int64_t n) {
+  return guarded([&] {
+    require(b != nullptr, "ovfem_batch_step_noalloc: batch is NULL");
+    require(n >= 0, "ovfem_batch_step_noalloc: n < 0");
+    b->check_members();
+    for (size_t i = 0; i < b->members.size(); ++i) {
+      const ovfem_solver* m = b->members[i];
+      require(m->model_set && m->dt_set, "ovfem_batch_step_noalloc: member " + std::to_string(i) +
+                                             " has no model or dt", OVFEM_ESTATE);
+      require(!m->acoef_dirty, "ovfem_batch_step_noalloc: member " + std::to_string(i) +
+                                   " changed since it last stepped; step it once (ovfem_step with n = 0) to "
+                                   "build its tables",
+              OVFEM_ESTATE);
+    }
+    if (n == 0) return;
+    b->tables(b->t_fixed, b->begin_fixed);
+    const size_t tb = b->t_fixed.size() * sizeof(KArgs), bb = b->begin_fixed.size() * sizeof(int);
+    require(tb + bb <= OVFEM_NOALLOC_SCRATCH_BYTES,
+            "ovfem_batch_step_noalloc: the batch's argument tables take " + std::to_string(tb + bb) +
+                " bytes (" + std::to_string(b->begin_fixed.size() - 1) + " units); the fixed array holds " +
+                std::to_string((size_t)OVFEM_NOALLOC_SCRATCH_BYTES));
+    unsigned char* p = scratch_address();
+    // stream-ordered after every earlier use of the array on this stream
+    OVFEM_HIP(hipMemcpyAsync(p, b->t_fixed.data(), tb, hipMemcpyHostToDevice, b->stream));
+    OVFEM_HIP(hipMemcpyAsync(p + tb, b->begin_fixed.data(), bb, hipMemcpyHostToDevice, b->stream));
+    b->launch(reinterpret_cast<const KArgs*>(p), reinterpret_cast<const int*>(p + tb), b->begin_fixed, n);
   });
 }
 

@@ -54,6 +54,7 @@ SIGNATURES = {
     "ovfem_batch_destroy": (_i32, [_vp]),
     "ovfem_batch_set_tuning": (_i32, [_vp, _i32]),
     "ovfem_batch_step": (_i32, [_vp, _i64]),
+    "ovfem_batch_step_noalloc": (_i32, [_vp, _i64]),
     "ovfem_check_finite": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "ovfem_synchronize": (_i32, [_vp]),
 }
@@ -364,6 +365,13 @@ class Batch:
         for m in self.members:
             m._touch()
         _check(_LIB.ovfem_batch_step(self._h, int(n)))
+
+    def step_noalloc(self, n=1):
+        """step() with the argument tables in the library's fixed device array (no device
+        allocation); every member must have stepped since it was last changed."""
+        for m in self.members:
+            m._touch()
+        _check(_LIB.ovfem_batch_step_noalloc(self._h, int(n)))
 
     def close(self):
         if self._h:
