@@ -23,12 +23,12 @@
 //     one power-of-two exponent S per element layer of the work-group (the paper
 //     scales each element by its own s_e; an exponent shared by the 17 x 17 x 2
 //     staged nodes of a layer lets a node's slices be computed once for the 4
-//     elements of the layer that touch it).  S is the smallest power of two above
-//     every staged value, taken from the staged values themselves (see
-//     StagingExponent); a node plane is staged again only when the next layer's S
-//     differs.  q is split into M balanced base-256 digits d_j in [-128, 127],
+//     elements of the layer that touch it).  2^S is the smallest power of two above
+//     every staged value with S a multiple of EXP_QUANT, taken from the staged values
+//     themselves (key_exponent); a node plane is staged again only when the next
+//     layer's S differs.  q is split into M balanced base-256 digits d_j in [-128, 127],
 //     QB = 8M - 2 (M = 8 by default: 62 bits, so every entry is represented to
-//     2^(S-63) absolutely, 2^-61 relative to the layer maximum; the paper: 8
+//     2^(S-63) absolutely, at least 2^-59 relative to the layer maximum; the paper: 8
 //     sign-magnitude base-128 digits of a 56-bit integer), and the digit
 //     products with the 48 x 24 integer matrix [AL; AM] run on the matrix cores, digits
 //     taken pairwise from the top.  PATH_INT8 uses v_mfma_i32_16x16x32_i8:
@@ -76,13 +76,14 @@ struct Stages {
 };
 constexpr int FPLANE = 3 * PN * PN;        // doubles per staged FP64 plane
 constexpr int NEXTRA = PN * PN - NTHR;     // staged nodes beyond one per thread (33)
-// Staging exponent of the INT8 paths.  S >= EXP_FLOOR keeps the scale factors
-// h lam / 256 2^(S-QB) normal (values below 2^(EXP_FLOOR-QB-1) round to 0); a layer
-// keeps the previous layer's S while L <= S <= L + EXP_SLACK (L: the exact exponent of
-// the layer's staged maximum), else S = L + EXP_HEAD and the shared plane is staged again.
+// Staging exponent of the INT8 paths: S is the exact exponent of the layer's staged
+// maximum rounded up to a multiple of EXP_QUANT (so a layer shares its neighbour's S, and
+// the plane they share is not staged again, unless the maximum moves across a multiple:
+// fewer restages for at most EXP_QUANT - 1 bits of the QB), and S >= EXP_FLOOR keeps the
+// scale factors h lam / 256 2^(S-QB) normal (values below 2^(EXP_FLOOR-QB-1) round to 0).
 constexpr int EXP_FLOOR = -900;
-constexpr int EXP_HEAD = 0;
-constexpr int EXP_SLACK = 0;
+constexpr int EXP_QUANT = 4;
+static_assert(EXP_FLOOR % EXP_QUANT == 0 && (EXP_QUANT & (EXP_QUANT - 1)) == 0, "staging exponent quantum");
 
 static_assert(kMaxRowAbs * 128 * 256 + kMaxRowAbs * 255 < (1 << 24),
               "digit-pair sums must be exact in FP32");
@@ -413,9 +414,11 @@ __device__ inline uint32_t node_key(const D3& v) {
   return max(mag_key(v.v[0]), max(mag_key(v.v[1]), mag_key(v.v[2])));
 }
 
-// Smallest exponent e >= EXP_FLOOR with |v| < 2^e for every v whose key is <= key.
+// Smallest multiple S of EXP_QUANT, S >= EXP_FLOOR, with |v| < 2^S for every v whose key
+// is <= key.
 __device__ inline int key_exponent(uint32_t key) {
-  return max(max((int)(key >> 20), 1) - 1022, EXP_FLOOR);
+  const int e = max(max((int)(key >> 20), 1) - 1022, EXP_FLOOR);
+  return (e + EXP_QUANT - 1) & ~(EXP_QUANT - 1);  // rounds up for negative e too
 }
 
 // Maximum over the wave (every lane gets it): DPP within rows of 16, then the four rows.
@@ -473,12 +476,12 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     for (int i = 0; i < 3; ++i) a_frag8[i] = (long)A.alane8[i * 64 + lane];
   }
 
-  // staged nodes: main node (ta+1, tb+1); 33 threads stage one more (extra node xi of
-  // the row q = 0 and the column p = 0 of the plane), dealt round-robin over the four
-  // waves (9, 8, 8, 8), so that no wave, and no SIMD, does a second node's loads and
-  // digit split alone while the others wait at the layer's barrier
-  const int xi = lane < (NEXTRA + 3) / 4 ? 4 * lane + wave : NEXTRA;
-  const bool has_extra = xi < NEXTRA;
+  // staged nodes: main node (ta+1, tb+1); the first 33 lanes of the last wave stage
+  // one more (the row q = 0 and the column p = 0 of the plane).  (Dealing the extra
+  // nodes over all four waves measured 5 % slower: every wave then issues the extra
+  // node's digit split, for 8 or 9 active lanes.)
+  const int xi = t - (NTHR - 64);
+  const bool has_extra = xi >= 0 && xi < NEXTRA;
   const int mp = ta + 1, mq = tb + 1;
   const int xp = xi < PN ? xi : 0, xq = xi < PN ? 0 : xi - (PN - 1);
   const NodeRef main_ref = node_ref(g, x0 - 1 + mp, y0 - 1 + mq);
@@ -557,8 +560,8 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   };
 
   // Staging exponent (INT8).  Layer it (planes rel it, it+1) needs every staged value
-  // below 2^S; L(it) = key_exponent of the larger key of the two planes is the exact
-  // bound.  key_top: the key of plane it+1 while layer it runs.
+  // below 2^S; S(it) = key_exponent of the larger key of the two planes.  key_top: the
+  // key of plane it+1 while layer it runs.
   uint32_t key_top = 0;
   bool restage = false;  // plane it (already staged for layer it-1) must be staged again
   if (F64) {
@@ -578,7 +581,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     __syncthreads();
     const uint32_t K0 = read_keys(0);
     key_top = read_keys(1);
-    S = key_exponent(max(K0, key_top)) + EXP_HEAD;
+    S = key_exponent(max(K0, key_top));
     stage(0, m0, x0);
   }
   fetch_mat(z0 - 1);
@@ -796,8 +799,8 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       const uint32_t key_new = read_keys(0);
       const int L = key_exponent(max(key_top, key_new));
       key_top = key_new;
-      restage = L > S || S - L > EXP_SLACK;
-      if (restage) S = L + EXP_HEAD;
+      restage = L != S;
+      S = L;
     }
 
     // ---- node phase for plane Z = k (owned when it >= 1)

@@ -8,8 +8,9 @@ the contract is stated per entry against that block:
   * the owner work-group of node n (tile T of 15 x 15 node columns, x0 = 15 tx, y0 = 15 ty)
     computes n's element contributions of layer kk (kk = k-1, k) from the staged block of
     nodes x0-1..x0+15, y0-1..y0+15, planes kk and kk+1 (0 outside the grid);
-  * its staging exponent is S(T, kk) = max(-900, e), e the exponent with 2^(e-1) <= m < 2^e
-    for the block's largest magnitude m (S = -900 when the block is all zero);
+  * its staging exponent S(T, kk) is max(-900, e) rounded up to a multiple of 4, e the
+    exponent with 2^(e-1) <= m < 2^e for the block's largest magnitude m (S = -900 when the
+    block is all zero);
   * every staged value v becomes q 2^(S-QB), q = rint(v 2^(QB-S)), QB = 8M - 2, an error of
     at most 2^(S-QB-1); the integer digit products are exact; the rest is FP64.
 
@@ -33,6 +34,7 @@ pytestmark = pytest.mark.gpu
 
 TN = 15          # owned node columns per tile side
 EXP_FLOOR = -900
+EXP_QUANT = 4
 SLACK = 64 * 2.0 ** -53
 
 
@@ -48,7 +50,8 @@ def _staging_exponents(u, nx, ny, nz):
             pm[:, ty, tx] = pad[:, TN * ty:TN * ty + TN + 2, TN * tx:TN * tx + TN + 2].max(axis=(1, 2))
     m = np.maximum(pm[:-1], pm[1:])
     e = np.frexp(m)[1]
-    return np.where(m > 0, np.maximum(e, EXP_FLOOR), EXP_FLOOR)
+    S = np.where(m > 0, np.maximum(e, EXP_FLOOR), EXP_FLOOR)
+    return -((-S) // EXP_QUANT) * EXP_QUANT
 
 
 def contract_bound(u, lam, mu, h, M):
