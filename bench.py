@@ -456,6 +456,18 @@ def main():
         runs[p] = PathRun(wls, p, rec_nt, batched, autotune=not args.no_autotune, chunk_planes=args.chunk_planes)
         ms = time_run(runs[p], args.warmup, args.steps)
         res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "tuning": runs[p].tuning}
+        if batched:
+            # the batch's steps replayed from captured graphs of 24 steps, against plain launches
+            runs[p].batch.set_graph(24)
+            ms_g = time_run(runs[p], args.warmup, args.steps)
+            res[p]["plain_ms_per_step"], res[p]["graph_ms_per_step"] = ms, ms_g
+            if ms_g < ms:
+                res[p].update(ms_per_step=ms_g, value=free_dof / (ms_g * 1e-3), tuning={"batch_graph_steps": 24})
+            else:
+                runs[p].batch.set_graph(0)
+                res[p]["tuning"] = {"batch_graph_steps": 0}
+            print("[bench] %s %s: batch plain %.4f ms/step, replayed graphs %.4f" % (args.workload, p, ms, ms_g),
+                  file=sys.stderr, flush=True)
         print("[bench] %s %s: %.4f ms/step, %.4e DOF-updates/s, tuning %s"
               % (args.workload, p, ms, res[p]["value"], runs[p].tuning), file=sys.stderr, flush=True)
     head = "int8" if "int8" in res else paths[0]
@@ -476,6 +488,8 @@ def main():
                  ("int8-digits(bf16-mfma,exact)+f64" if head == "int8-bf16" else "f64"),
         "data": "synthetic",
         "config": {"workload": desc, "path": head, "tuning": res[head]["tuning"],
+                   "batch_plain_vs_graph_ms": ({p: [res[p]["plain_ms_per_step"], res[p]["graph_ms_per_step"]]
+                                                for p in res} if batched else None),
                    "domains": [[w.nx, w.ny, w.nz, w.n_shots] for w in wls] if len(wls) > 1 else
                    [wls[0].nx, wls[0].ny, wls[0].nz, wls[0].n_shots]},
         "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",

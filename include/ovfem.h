@@ -277,6 +277,14 @@ ovfem_status ovfem_batch_destroy(ovfem_batch* b);
 /* Grid cap of the batched launch, as persistent_groups of ovfem_set_tuning (0 = none). */
 ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups);
 
+/* Replay whole blocks of graph_steps batch steps from a captured HIP graph (a multiple of
+ * 6 in 0..4096; 0, the default, launches every step from the host).  A block starts at a
+ * batch step that is a multiple of 6 (steps before it, and the remainder, are launched
+ * plainly); the graph reads the step base from device memory and is captured again when
+ * the batch's argument tables move or its launch shape changes.  Damped batches are not
+ * captured.  Results are bitwise those of plain launches.  Waits for the stream. */
+ovfem_status ovfem_batch_set_graph(ovfem_batch* b, int32_t graph_steps);
+
 /* Enqueue n >= 0 steps of every member (asynchronous).  Each member advances exactly as
  * ovfem_step(member, n) would (bitwise: the same kernels on the same tiles), from its
  * own step counter.  Members must share one precision (and stage count) and have model and dt set

@@ -67,6 +67,11 @@ __global__ void fill_random_kernel(double* v, size_t n, unsigned long long seed,
   v[i] = scale * ((double)(z >> 11) * 0x1p-52 - 1.0);
 }
 
+// *p = v (a device step base set in stream order, without a host value to keep alive).
+__global__ void set_step_kernel(long long* p, long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 template <class F>
 ovfem_status guarded(F&& f) {
   try {
@@ -651,10 +656,61 @@ struct ovfem_batch {
   DevBuf<int> begin;
   std::vector<KArgs> t_fixed;  // host side of ovfem_batch_step_noalloc's tables (capacity kept)
   std::vector<int> begin_fixed;
+  // captured blocks of graph_steps (a multiple of kBatchTables) batch steps starting at a
+  // batch step B = 0 (mod kBatchTables), replayed with the step base in device memory
+  int graph_steps = 0;
+  hipGraphExec_t graph = nullptr;
+  const KArgs* graph_units = nullptr;  // the tables and launch shape the graph was captured with
+  int graph_n_units = -1, graph_total = -1, graph_persist = -1, graph_form = -1;
+  DevBuf<long long> step_base;
   ~ovfem_batch() {
     (void)hipStreamSynchronize(stream);
+    drop_graph();
     units.free();
     begin.free();
+    step_base.free();
+  }
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+    graph_units = nullptr;
+  }
+
+  // capture graph_steps launches at B = base + i, B = i (mod kBatchTables), then the
+  // advance of the base
+  void capture(const KArgs* units_d, const int* begin_d, int n_units, int total) {
+    drop_graph();
+    if (!step_base.p) step_base.alloc(1);
+    const Form form = members[0]->form();
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    OVFEM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    try {
+      OVFEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int i = 0; i < graph_steps; ++i)
+          launch_units(form, units_d + (size_t)(i % kBatchTables) * n_units, begin_d, n_units, total, persist_groups,
+                       step_base.p, i, cs);
+        ovfem_advance_step_kernel<<<1, 64, 0, cs>>>(step_base.p, graph_steps);
+        OVFEM_HIP(hipGetLastError());
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &g);
+        throw;
+      }
+      OVFEM_HIP(hipStreamEndCapture(cs, &g));
+      OVFEM_HIP(hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));
+    } catch (...) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      throw;
+    }
+    (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    graph_units = units_d;
+    graph_n_units = n_units;
+    graph_total = total;
+    graph_persist = persist_groups;
+    graph_form = members[0]->form_code();
   }
 
   // validate the members for a batched launch; returns the work-item count
@@ -693,15 +749,33 @@ struct ovfem_batch {
   }
 
   // enqueue n steps reading the device tables units_d / begin_d (bg: the host copy of
-  // begin_d), then advance the members
-  void launch(const KArgs* units_d, const int* begin_d, const std::vector<int>& bg, int64_t n) {
+  // begin_d), then advance the members.  With use_graph, whole blocks of graph_steps
+  // steps that start at B = 0 (mod kBatchTables) are replayed from a captured graph.
+  void launch(const KArgs* units_d, const int* begin_d, const std::vector<int>& bg, int64_t n, bool use_graph) {
     const Form form = members[0]->form();
     const int n_units = (int)bg.size() - 1, total = bg.back();
-    for (int64_t i = 0; i < n; ++i) {
-      const long long B = steps + i;
-      launch_units(form, units_d + (size_t)(B % kBatchTables) * n_units, begin_d, n_units, total, persist_groups,
-                   nullptr, B, stream);
+    int64_t i = 0;
+    auto plain = [&](int64_t upto) {
+      for (; i < upto; ++i) {
+        const long long B = steps + i;
+        launch_units(form, units_d + (size_t)(B % kBatchTables) * n_units, begin_d, n_units, total, persist_groups,
+                     nullptr, B, stream);
+      }
+    };
+    if (use_graph && graph_steps > 0 && !form.damp) {
+      const int64_t lead = (kBatchTables - steps % kBatchTables) % kBatchTables;
+      if (n - lead >= graph_steps) {
+        plain(lead);
+        const int code = members[0]->form_code();
+        if (!graph || graph_units != units_d || graph_n_units != n_units || graph_total != total ||
+            graph_persist != persist_groups || graph_form != code)
+          capture(units_d, begin_d, n_units, total);
+        set_step_kernel<<<1, 64, 0, stream>>>(step_base.p, steps + i);
+        OVFEM_HIP(hipGetLastError());
+        for (; i + graph_steps <= n; i += graph_steps) OVFEM_HIP(hipGraphLaunch(graph, stream));
+      }
     }
+    plain(n);
     for (auto* m : members) {
       for (int64_t i = 0; i < n % m->n_phase(); ++i) m->phase = m->buf_next(m->phase);
       m->step += n;
@@ -1426,6 +1500,17 @@ ovfem_status ovfem_batch_set_tuning(ovfem_batch* b, int32_t persistent_groups) {
   });
 }
 
+ovfem_status ovfem_batch_set_graph(ovfem_batch* b, int32_t graph_steps) {
+  return guarded([&] {
+    require(b != nullptr, "ovfem_batch_set_graph: batch is NULL");
+    require(graph_steps >= 0 && graph_steps % kBatchTables == 0 && graph_steps <= 4096,
+            "ovfem_batch_set_graph: graph_steps must be a multiple of 6 in 0..4096");
+    OVFEM_HIP(hipStreamSynchronize(b->stream));
+    b->drop_graph();
+    b->graph_steps = graph_steps;
+  });
+}
+
 ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
   return guarded([&] {
     require(b != nullptr, "ovfem_batch_step: batch is NULL");
@@ -1441,6 +1526,7 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
     if (!same) {
       if (b->units.n < t.size() || b->begin.n < bg.size()) {
         OVFEM_HIP(hipStreamSynchronize(b->stream));  // earlier launches may still read the old tables
+        b->drop_graph();
         b->units.alloc(t.size());
         b->begin.alloc(bg.size());
       }
@@ -1452,7 +1538,7 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n) {
       OVFEM_HIP(hipMemcpyAsync(b->begin.p, b->begin_host.data(), b->begin_host.size() * sizeof(int),
                                hipMemcpyHostToDevice, b->stream));
     }
-    b->launch(b->units.p, b->begin.p, b->begin_host, n);
+    b->launch(b->units.p, b->begin.p, b->begin_host, n, true);
   });
 }
 
@@ -1481,7 +1567,7 @@ ovfem_status ovfem_batch_step_noalloc(ovfem_batch* b, int64_t n) {
     // stream-ordered after every earlier use of the array on this stream
     OVFEM_HIP(hipMemcpyAsync(p, b->t_fixed.data(), tb, hipMemcpyHostToDevice, b->stream));
     OVFEM_HIP(hipMemcpyAsync(p + tb, b->begin_fixed.data(), bb, hipMemcpyHostToDevice, b->stream));
-    b->launch(reinterpret_cast<const KArgs*>(p), reinterpret_cast<const int*>(p + tb), b->begin_fixed, n);
+    b->launch(reinterpret_cast<const KArgs*>(p), reinterpret_cast<const int*>(p + tb), b->begin_fixed, n, false);
   });
 }
 

@@ -53,6 +53,7 @@ SIGNATURES = {
     "ovfem_batch_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32]),
     "ovfem_batch_destroy": (_i32, [_vp]),
     "ovfem_batch_set_tuning": (_i32, [_vp, _i32]),
+    "ovfem_batch_set_graph": (_i32, [_vp, _i32]),
     "ovfem_batch_step": (_i32, [_vp, _i64]),
     "ovfem_batch_step_noalloc": (_i32, [_vp, _i64]),
     "ovfem_check_finite": (_i32, [_vp, ctypes.POINTER(_i32)]),
@@ -360,6 +361,10 @@ class Batch:
 
     def set_tuning(self, persistent_groups=0):
         _check(_LIB.ovfem_batch_set_tuning(self._h, int(persistent_groups)))
+
+    def set_graph(self, graph_steps):
+        """Replay blocks of graph_steps (a multiple of 6) steps from a captured graph."""
+        _check(_LIB.ovfem_batch_set_graph(self._h, int(graph_steps)))
 
     def step(self, n=1):
         for m in self.members:

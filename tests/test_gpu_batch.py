@@ -123,6 +123,39 @@ def test_uneven_batch_matches_individual_runs(prec):
         assert m.get_step() == (70 if k == 1 else 65)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "int8"])
+def test_uneven_batch_replayed_from_captured_graphs(prec):
+    """Blocks of 12 batch steps replayed from a captured graph (step base in device memory),
+    with eager reads between the calls, uneven call lengths that start off the block
+    boundary, a member stepped alone in between (its tables are uploaded again), a grid cap
+    switched on, and the graph switched off: bitwise the plain per-step launches."""
+    from paper_2404_13683_amd.ovfem import Batch
+    doms = wl.uneven_domains_c3(n_domains=3, smallest=(10, 12, 9), largest=(34, 30, 20), nt=140, n_rec=4, seed=12)
+    shots = _small_shots(n_shots=2, nt=140)
+    work = doms + [shots]
+    plain = [_solver(d, prec) for d in work]
+    graph = [_solver(d, prec) for d in work]
+    bp, bg = Batch(plain), Batch(graph)
+    bg.set_graph(12)
+    for n in (5, 31, 24):
+        bp.step(n)
+        bg.step(n)
+        _same(_state(graph[0]), _state(plain[0]))  # eager work between replays
+    plain[2].step(3)
+    graph[2].step(3)
+    for b in (bp, bg):
+        b.set_tuning(persistent_groups=16)
+        b.step(40)
+    bg.set_graph(0)
+    bp.step(7)
+    bg.step(7)
+    for b in (bp, bg):
+        b.close()
+    for a, m in zip(plain, graph):
+        _same(_state(m), _state(a))
+    assert graph[2].get_step() == 110 and graph[0].get_step() == 107
+
+
 def test_batch_rejects_mixed_precision():
     from paper_2404_13683_amd.ovfem import Batch, OvfemError
     d = wl.uneven_domains_c3(n_domains=2, smallest=(8, 8, 8), largest=(12, 10, 9), nt=10, n_rec=2)
