@@ -84,12 +84,16 @@ def _counter_values(workload):
 
 
 def measured_traffic(workload, path_name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by the copy-kernel factors), if taken on the current kernel source."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if taken on the
+    current kernel source: the bytes of the L2-to-memory read and write requests counted by
+    size (32, 64, 128 B) when the summary has them, else FETCH_SIZE + WRITE_SIZE scaled by the
+    copy-kernel factors."""
     kv = _counter_values(workload)
     if kv is None:
         return None
     try:
+        if "%s_read_bytes" % path_name in kv:
+            return float(kv["%s_read_bytes" % path_name]) + float(kv["%s_write_bytes" % path_name])
         f = float(kv["%s_fetch_kib" % path_name]) * float(kv["fetch_factor"])
         w = float(kv["%s_write_kib" % path_name]) * float(kv["write_factor"])
     except KeyError:
