@@ -205,7 +205,8 @@ class PathRun:
     """The solvers of one element-product path for a workload (one solver with all shots,
     or a batch of uneven solvers), kept open between the timed and the full-length legs."""
 
-    def __init__(self, wls, prec, rec_nt, batched, autotune=True, chunk_planes=0, stages=8, element="ovfem"):
+    def __init__(self, wls, prec, rec_nt, batched, autotune=True, chunk_planes=0, stages=8, element="ovfem",
+                 tile_rows=16):
         from paper_2404_13683_amd.ovfem import Batch, Solver
         self.solvers = [Solver.from_workload(w, precision=prec, receivers_nt=rec_nt, element=element)
                         for w in wls]
@@ -215,7 +216,7 @@ class PathRun:
                 s.set_stages(stages)
             if not batched:
                 if chunk_planes:
-                    s.set_tuning(chunk_planes=chunk_planes)
+                    s.set_tuning(chunk_planes=chunk_planes, tile_rows=tile_rows)
                 elif autotune:
                     s.autotune(steps=20)
         self.tuning = None if batched else self.solvers[0].get_tuning()
@@ -421,6 +422,8 @@ def main():
                     choices=["c5", "c2", "c3-shots", "c3-uneven", "c5-slab", "c4-adjoint"])
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--chunk-planes", type=int, default=0, help="fixed z-chunk depth instead of autotuning")
+    ap.add_argument("--tile-rows", type=int, default=16, choices=[16, 32],
+                    help="tile height with --chunk-planes (element rows per work-group)")
     ap.add_argument("--no-equal-accuracy", action="store_true", help="skip the trilinear comparison")
     ap.add_argument("--no-full-run", action="store_true",
                     help="skip the untimed full-length trace comparison between the paths")
@@ -457,7 +460,8 @@ def main():
     paths = args.paths.split(",")
     runs, res = {}, {}
     for p in paths:
-        runs[p] = PathRun(wls, p, rec_nt, batched, autotune=not args.no_autotune, chunk_planes=args.chunk_planes)
+        runs[p] = PathRun(wls, p, rec_nt, batched, autotune=not args.no_autotune, chunk_planes=args.chunk_planes,
+                          tile_rows=args.tile_rows)
         ms = time_run(runs[p], args.warmup, args.steps)
         res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "tuning": runs[p].tuning}
         if batched:

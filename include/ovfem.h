@@ -254,9 +254,20 @@ ovfem_status ovfem_set_tuning(ovfem_solver* s, int32_t chunk_planes, int32_t per
 ovfem_status ovfem_get_tuning(ovfem_solver* s, int32_t* chunk_planes, int32_t* persistent_groups,
                               int32_t* graph_steps);
 
+/* Tile height of the stepper kernels: rows = 16 (16 x 16 elements per work-group of 256
+ * threads, 15 x 15 owned node columns; the default) or 32 (16 x 32 elements, 512 threads,
+ * 15 x 31 owned node columns: a smaller halo, fewer tiles on grids whose node count per
+ * row is just above a multiple of 15).  FP64 results are bitwise the same for both; INT8
+ * results depend on the staged blocks (the staging exponent's extent) within the accuracy
+ * bound of the staging exponent.  Rebuilds the tile tables (waits for the stream); a
+ * checkpointed forward run is invalidated.  EINVAL for other values. */
+ovfem_status ovfem_set_tile_rows(ovfem_solver* s, int32_t rows);
+ovfem_status ovfem_get_tile_rows(ovfem_solver* s, int32_t* rows);
+
 /* Autotuner: times `steps` (2..100000) plain-launch steps of the solver's own model,
- * sources and precision for each candidate chunk depth (8, 12, 16, 24, 32, 48, 64, 96
- * planes, each evened out over the chunks it gives) and, for n_shots > 1, grid caps of
+ * sources and precision for each tile height (16 and 32 element rows) and candidate chunk
+ * depth (8, 12, 16, 24, 32, 48, 64, 96 planes, each evened out over the chunks it gives)
+ * and, for n_shots > 1, grid caps of
  * 0, 2 and 4 work-groups per compute unit, keeps the fastest, then times graph_steps 0
  * and 64 at that setting and keeps the faster.  The wavefield pair, traces and step counter are
  * restored afterwards; a checkpointed forward run is invalidated.  best_ms_per_step

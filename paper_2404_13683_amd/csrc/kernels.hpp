@@ -53,13 +53,12 @@ namespace ovfem {
 constexpr int TE = 16;        // element columns per tile side
 constexpr int TN = TE - 1;    // owned node columns per tile side
 constexpr int PN = TE + 1;    // node columns per staged plane side
-constexpr int NTHR = 256;     // threads per work-group
+constexpr int NTHR = 256;     // threads per work-group of the one-element-per-thread kernels
 constexpr int NPAIR = 4;      // digit pairs (M = 8 digits)
 constexpr int QBITS = 62;     // fraction bits of q under the tile exponent
 constexpr int NODE_DW = 16;   // dwords of one staged node: 4 pairs x (hi, lo) x 2 dwords
 // digit plane layout [row q][pair p][hi/lo][column x][2 dwords]: the B operand of a
 // lane (its element's nodes x and x+1 in one row) is 16 contiguous bytes
-constexpr int DPLANE = PN * PN * NODE_DW;  // dwords per staged digit plane
 constexpr int DROW = NPAIR * 2 * PN * 2;   // dwords per staged digit row
 // i8 form with M digits (stages): [row q][digit j][column x] one dword (c0, c1, c2, 0)
 // of signed digits.  Rows are padded to 16 (mod 64) dwords and planes to 32 (mod 64),
@@ -74,8 +73,22 @@ struct Stages {
   static constexpr int ROW = pad_to(M * PN, 16);
   static constexpr int PLANE = pad_to(PN * ROW, 32);
 };
-constexpr int FPLANE = 3 * PN * PN;        // doubles per staged FP64 plane
-constexpr int NEXTRA = PN * PN - NTHR;     // staged nodes beyond one per thread (33)
+// Tile height: TY element rows per work-group (16 or 32), 16 TY threads, TY / 4 waves of
+// four tile rows each; TY - 1 owned node rows.  The x extent is TE (the matrix-core columns).
+template <int TY>
+struct Tile {
+  static_assert(TY == 16 || TY == 32, "tile heights of 16 or 32 element rows");
+  static constexpr int THREADS = TE * TY;
+  static constexpr int WAVES = THREADS / 64;
+  static constexpr int NY = TY - 1;                     // owned node rows
+  static constexpr int PNY = TY + 1;                    // staged node rows
+  static constexpr int EXTRA = PN * PNY - THREADS;      // staged nodes beyond one per thread
+  static constexpr int FPLANE = 3 * PN * PNY;           // doubles per staged FP64 plane
+  static constexpr int DPLANE = PN * PNY * NODE_DW;     // dwords per staged bf16 digit plane
+  template <int M>
+  static constexpr int iplane() { return pad_to(PNY * Stages<M>::ROW, 32); }  // dwords per i8 digit plane
+  static_assert(EXTRA > 0 && EXTRA <= 64, "the extra staged nodes fit in the last wave");
+};
 // Staging exponent of the INT8 paths: S is the exact exponent of the layer's staged
 // maximum rounded up to a multiple of EXP_QUANT (so a layer shares its neighbour's S, and
 // the plane they share is not staged again, unless the maximum moves across a multiple:
@@ -95,6 +108,11 @@ enum : int { MODE_STEP = 0, MODE_MATVEC = 1 };
 // PATH_FP64SF: the element product in FP64, sum-factorised (sf_transform, sf_component).
 enum : int { PATH_FP64 = 0, PATH_INT8 = 1, PATH_BF16 = 2, PATH_FP64SF = 3 };
 constexpr bool is_f64_path(int p) { return p == PATH_FP64 || p == PATH_FP64SF; }
+// work-groups per CU named in the launch bounds: the i8 kernels are held to 128 registers
+// (four waves per SIMD), the bf16 ones to 256 / 2, the FP64 ones left free
+constexpr int groups_per_cu(int path, int ty) {
+  return is_f64_path(path) ? 1 : (path == PATH_INT8 ? (ty == 16 ? 4 : 2) : (ty == 16 ? 2 : 1));
+}
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -106,6 +124,7 @@ struct Geom {
   int tz;          // node planes per chunk
   int tiles_x, tiles_y, chunks;
   int n_wg;
+  int ty;          // element rows per tile (Tile<TY>; the kernel's template argument)
 };
 
 struct KArgs {
@@ -440,25 +459,29 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 // kernel then fits 128 VGPRs, four waves per SIMD).
 // ELEM: element matrices of the FP64 path (0 OVFEM, 1 trilinear); the INT8 paths take
 // theirs from the A-operand tables.
-template <int PATH, int MODE, int M, bool DAMP = false, bool LATE = false, int ELEM = 0>
+// TY: element rows of the tile (Tile<TY>).
+template <int PATH, int MODE, int M, bool DAMP = false, bool LATE = false, int ELEM = 0, int TY = 16>
 __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const long long step) {
   static_assert(!DAMP || MODE == MODE_STEP, "damping applies to time steps");
   using St = Stages<M>;
+  using Tl = Tile<TY>;
+  constexpr int NT = Tl::THREADS, PNY = Tl::PNY;
+  constexpr int IPLANE = Tl::template iplane<M>();
   constexpr int QB = PATH == PATH_INT8 ? St::QB : QBITS;
   const Geom g = A.g;
   const int tx = wg % g.tiles_x, ty = (wg / g.tiles_x) % g.tiles_y, tzc = wg / (g.tiles_x * g.tiles_y);
-  const int x0 = tx * TN, y0 = ty * TN, z0 = tzc * g.tz;
+  const int x0 = tx * TN, y0 = ty * Tl::NY, z0 = tzc * g.tz;
   const int z1 = min(z0 + g.tz, g.nz + 1);  // owned planes [z0, z1)
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int ta = t & 15, tb = t >> 4;       // element column (ta, tb); main staged node (ta+1, tb+1)
 
   // in-plane node sums: lsum[q] from elements of row q, usum[q-1] from elements of row q-1
-  __shared__ double lsum[TE * 3 * TE];  // [q][c][p], q = 0..15
-  __shared__ double usum[TE * 3 * TE];  // [q-1][c][p], q = 1..16
-  __shared__ __attribute__((aligned(16))) uint32_t keys[2][4];  // per wave: magnitude keys of staged planes
+  __shared__ double lsum[TY * 3 * TE];  // [q][c][p], q = 0..TY-1
+  __shared__ double usum[TY * 3 * TE];  // [q-1][c][p], q = 1..TY
+  __shared__ __attribute__((aligned(16))) uint32_t keys[2][Tl::WAVES];  // per wave: magnitude keys of staged planes
   constexpr bool F64 = is_f64_path(PATH);
-  __shared__ __attribute__((aligned(16))) double matl[F64 ? 2 : 2 * NTHR];  // slices: [b][a] material
-  constexpr int RING_BYTES = F64 ? 2 * FPLANE * 8 : (PATH == PATH_BF16 ? 2 * DPLANE * 4 : 2 * St::PLANE * 4);
+  __shared__ __attribute__((aligned(16))) double matl[F64 ? 2 : 2 * NT];  // slices: [b][a] material
+  constexpr int RING_BYTES = F64 ? 2 * Tl::FPLANE * 8 : (PATH == PATH_BF16 ? 2 * Tl::DPLANE * 4 : 2 * IPLANE * 4);
   __shared__ __attribute__((aligned(16))) unsigned char ring_raw[RING_BYTES];
   double* ringf = reinterpret_cast<double*>(ring_raw);
   uint32_t* ringd = reinterpret_cast<uint32_t*>(ring_raw);
@@ -476,18 +499,18 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
     for (int i = 0; i < 3; ++i) a_frag8[i] = (long)A.alane8[i * 64 + lane];
   }
 
-  // staged nodes: main node (ta+1, tb+1); the first 33 lanes of the last wave stage
+  // staged nodes: main node (ta+1, tb+1); the first TY + 17 lanes of the last wave stage
   // one more (the row q = 0 and the column p = 0 of the plane).  (Dealing the extra
-  // nodes over all four waves measured 5 % slower: every wave then issues the extra
-  // node's digit split, for 8 or 9 active lanes.)
-  const int xi = t - (NTHR - 64);
-  const bool has_extra = xi >= 0 && xi < NEXTRA;
+  // nodes over all the waves measured 5 % slower: every wave then issues the extra
+  // node's digit split, for a few active lanes.)
+  const int xi = t - (NT - 64);
+  const bool has_extra = xi >= 0 && xi < Tl::EXTRA;
   const int mp = ta + 1, mq = tb + 1;
   const int xp = xi < PN ? xi : 0, xq = xi < PN ? 0 : xi - (PN - 1);
   const NodeRef main_ref = node_ref(g, x0 - 1 + mp, y0 - 1 + mq);
   const NodeRef extra_ref = node_ref(g, x0 - 1 + xp, y0 - 1 + xq);
   const ElemRef elem = elem_ref(g, x0 - 1 + ta, y0 - 1 + tb);
-  const bool owner = ta < TN && tb < TN;  // owns node (x0+ta, y0+tb) = plane (ta+1, tb+1)
+  const bool owner = ta < TN && tb < Tl::NY;  // owns node (x0+ta, y0+tb) = plane (ta+1, tb+1)
   const bool owner_in = owner && main_ref.xy_ok;
   const size_t plane_bytes = (size_t)24 * (g.nx + 1) * (g.ny + 1);
   const size_t layer_bytes = (size_t)16 * g.nx * g.ny;
@@ -537,26 +560,31 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
   };
   auto stage = [&](int slot, const D3& m, const D3& x) {
     if (F64) {
-      double* P = ringf + slot * FPLANE;
+      double* P = ringf + slot * Tl::FPLANE;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) P[(c * PN + mq) * PN + mp] = m.v[c];
+      for (int c = 0; c < 3; ++c) P[(c * PNY + mq) * PN + mp] = m.v[c];
       if (has_extra)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) P[(c * PN + xq) * PN + xp] = x.v[c];
+        for (int c = 0; c < 3; ++c) P[(c * PNY + xq) * PN + xp] = x.v[c];
     } else if (PATH == PATH_BF16) {
-      uint32_t* P = ringd + slot * DPLANE;
+      uint32_t* P = ringd + slot * Tl::DPLANE;
       stage_digits(m, S, P + mq * DROW + 2 * mp);
       if (has_extra) stage_digits(x, S, P + xq * DROW + 2 * xp);
     } else {
-      uint32_t* P = ringd + slot * St::PLANE;
+      uint32_t* P = ringd + slot * IPLANE;
       stage_digits_i8<M>(m, S, P + mq * St::ROW + mp);
       if (has_extra) stage_digits_i8<M>(x, S, P + xq * St::ROW + xp);
     }
   };
   // work-group maximum of the keys written by the four waves into keys[slot]
   auto read_keys = [&](int slot) -> uint32_t {
-    const uint4 k4 = *reinterpret_cast<const uint4*>(keys[slot]);
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)max(max(k4.x, k4.y), max(k4.z, k4.w)));
+    uint32_t k = 0;
+#pragma unroll
+    for (int w4 = 0; w4 < Tl::WAVES; w4 += 4) {
+      const uint4 k4 = *reinterpret_cast<const uint4*>(keys[slot] + w4);
+      k = max(k, max(max(k4.x, k4.y), max(k4.z, k4.w)));
+    }
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
   };
 
   // Staging exponent (INT8).  Layer it (planes rel it, it+1) needs every staged value
@@ -636,15 +664,15 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       // sums of plane k; top-corner contributions are kept for plane k + 1
       double y[24];
       if (layer_ok) {
-        const double* Pb = ringf + bot * FPLANE;
-        const double* Pt = ringf + top * FPLANE;
+        const double* Pb = ringf + bot * Tl::FPLANE;
+        const double* Pt = ringf + top * Tl::FPLANE;
         double ue[24];
 #pragma unroll
         for (int alpha = 0; alpha < 8; ++alpha) {
           const int di = alpha & 1, dj = (alpha >> 1) & 1, dk = alpha >> 2;
           const double* P = dk ? Pt : Pb;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PN + tb + dj) * PN + ta + di];
+          for (int c = 0; c < 3; ++c) ue[3 * alpha + c] = P[(c * PNY + tb + dj) * PN + ta + di];
         }
         if constexpr (PATH == PATH_FP64SF) {
           // one output component at a time (fewer live registers)
@@ -682,7 +710,7 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
       }
     } else {
       const int ja = lane & 15, G = lane >> 4;  // element column; lane group
-      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_BF16 ? DPLANE : St::PLANE);
+      const uint32_t* Pin = ringd + ((G >> 1) ? top : bot) * (PATH == PATH_BF16 ? Tl::DPLANE : IPLANE);
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         const int b = 4 * wave + tt;
@@ -858,8 +886,8 @@ __device__ __forceinline__ void layer_tile(const KArgs& A, const int wg, const l
 // can be replayed with a step base kept in device memory.  The i8 kernels are held to
 // four waves per SIMD (128 registers): the damped and the 6-digit forms otherwise take
 // 129-131 and drop to three, which costs them 8-9 %.
-template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_INT8 ? 4 : 2))
+template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0, int TY = 16>
+__global__ void __launch_bounds__(Tile<TY>::THREADS, groups_per_cu(PATH, TY))
     ovfem_layer_kernel(KArgs A, const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
   const int units = A.n_units > 1 ? A.n_units : 1;
@@ -872,7 +900,7 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_IN
     A.src_ptr += v * A.unit_src;
     A.traces += v * A.unit_tr;
   }
-  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, item - v * A.g.n_wg, s);
+  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM, TY>(A, item - v * A.g.n_wg, s);
 }
 
 // Many units in one launch (grids of uneven size, each with its shots): unit u owns work
@@ -886,7 +914,7 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_IN
 // invariant loads let the compiler treat the fields as it treats kernel arguments (the
 // i8 batch kernel then fits in 128 registers instead of 144).
 __device__ inline KArgs load_unit(const KArgs* units, int v) {
-  static_assert(sizeof(KArgs) == 240, "load_unit copies every field of KArgs: keep the two in step");
+  static_assert(sizeof(KArgs) == 248, "load_unit copies every field of KArgs: keep the two in step");
   using CK = const __attribute__((address_space(4))) KArgs;
   CK* p = reinterpret_cast<CK*>(reinterpret_cast<uintptr_t>(units)) + v;
   KArgs a;
@@ -898,6 +926,7 @@ __device__ inline KArgs load_unit(const KArgs* units, int v) {
   a.g.tiles_y = p->g.tiles_y;
   a.g.chunks = p->g.chunks;
   a.g.n_wg = p->g.n_wg;
+  a.g.ty = p->g.ty;
   a.u = p->u;
   a.uprev = p->uprev;
   a.unext = p->unext;
@@ -938,19 +967,19 @@ __device__ inline int find_unit(const int* unit_begin, int n_units, int item) {
   return lo;
 }
 
-template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : (PATH == PATH_INT8 ? 4 : 2))
+template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0, int TY = 16>
+__global__ void __launch_bounds__(Tile<TY>::THREADS, groups_per_cu(PATH, TY))
     ovfem_batch_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                        const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
   const int item = logical_tile(blockIdx.x, total);
   const int v = find_unit(unit_begin, n_units, item);
   const KArgs A = load_unit(units, v);
-  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM>(A, item - unit_begin[v], s + A.step);
+  layer_tile<PATH, MODE, M, DAMP, PATH == PATH_INT8, ELEM, TY>(A, item - unit_begin[v], s + A.step);
 }
 
-template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0>
-__global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
+template <int PATH, int MODE, int M = 8, bool DAMP = false, int ELEM = 0, int TY = 16>
+__global__ void __launch_bounds__(Tile<TY>::THREADS, is_f64_path(PATH) || TY == 32 ? 1 : 2)
     ovfem_batch_strided_kernel(const KArgs* units, const int* unit_begin, int n_units, int total,
                                const long long* step_base, long long step) {
   const long long s = (step_base ? *step_base : 0) + step;
@@ -958,7 +987,7 @@ __global__ void __launch_bounds__(NTHR, is_f64_path(PATH) ? 1 : 2)
     const int item = logical_tile(b, total);
     const int v = find_unit(unit_begin, n_units, item);
     const KArgs A = load_unit(units, v);
-    layer_tile<PATH, MODE, M, DAMP, false, ELEM>(A, item - unit_begin[v], s + A.step);
+    layer_tile<PATH, MODE, M, DAMP, false, ELEM, TY>(A, item - unit_begin[v], s + A.step);
     __syncthreads();  // LDS is reused by the next work item
   }
 }

@@ -10,20 +10,22 @@
 namespace ovfem {
 
 // One record of KArgs (A.n_units shots at fixed strides): one work-group per tile and
-// shot.  mode: MODE_STEP or MODE_MATVEC; damp: Rayleigh-damped step.
+// shot.  ty: tile height in element rows (16 or 32, Tile<TY>); mode: MODE_STEP or
+// MODE_MATVEC; damp: Rayleigh-damped step.
 template <int PATH, int M, int ELEM>
-void launch_tiles(int mode, bool damp, const KArgs& A, const long long* base, long long step, hipStream_t stream);
+void launch_tiles(int ty, int mode, bool damp, const KArgs& A, const long long* base, long long step,
+                  hipStream_t stream);
 
 // A work list of units with their own records; grid < total selects the strided kernel.
 template <int PATH, int M, int ELEM>
-void launch_list(bool damp, int grid, const KArgs* units, const int* begin, int n_units, int total,
-                  const long long* base, long long step, hipStream_t stream);
+void launch_list(int ty, bool damp, int grid, const KArgs* units, const int* begin, int n_units, int total,
+                 const long long* base, long long step, hipStream_t stream);
 
 #define OVFEM_DECLARE_LAUNCHERS(PATH, M, ELEM)                                                                   \
-  extern template void launch_tiles<PATH, M, ELEM>(int, bool, const KArgs&, const long long*, long long,         \
+  extern template void launch_tiles<PATH, M, ELEM>(int, int, bool, const KArgs&, const long long*, long long,    \
                                                    hipStream_t);                                                \
-  extern template void launch_list<PATH, M, ELEM>(bool, int, const KArgs*, const int*, int, int,                \
-                                                   const long long*, long long, hipStream_t);
+  extern template void launch_list<PATH, M, ELEM>(int, bool, int, const KArgs*, const int*, int, int,           \
+                                                  const long long*, long long, hipStream_t);
 
 OVFEM_DECLARE_LAUNCHERS(PATH_FP64, 8, 0)
 OVFEM_DECLARE_LAUNCHERS(PATH_FP64, 8, 1)

@@ -197,6 +197,7 @@ struct Form {
   int stages;
   bool damp;  // Rayleigh-damped step kernels
   int elem;   // OVFEM_ELEMENT_*: selects the FP64 path's compile-time element matrices
+  int ty;     // tile height in element rows (16 or 32)
 };
 
 // One record, one work-group per tile (and shot).
@@ -205,24 +206,24 @@ void launch_unit(Form f, const KArgs& A, const long long* base, long long step, 
   const bool d = MODE == MODE_STEP && f.damp;
   if (f.precision == OVFEM_FP64) {
     if (f.elem == OVFEM_ELEMENT_TRILINEAR)
-      launch_tiles<PATH_FP64, 8, 1>(MODE, d, A, base, step, stream);
+      launch_tiles<PATH_FP64, 8, 1>(f.ty, MODE, d, A, base, step, stream);
     else
-      launch_tiles<PATH_FP64, 8, 0>(MODE, d, A, base, step, stream);
+      launch_tiles<PATH_FP64, 8, 0>(f.ty, MODE, d, A, base, step, stream);
   } else if (f.precision == OVFEM_INT8) {
     switch (f.stages) {
-      case 4: launch_tiles<PATH_INT8, 4, 0>(MODE, d, A, base, step, stream); break;
-      case 5: launch_tiles<PATH_INT8, 5, 0>(MODE, d, A, base, step, stream); break;
-      case 6: launch_tiles<PATH_INT8, 6, 0>(MODE, d, A, base, step, stream); break;
-      case 7: launch_tiles<PATH_INT8, 7, 0>(MODE, d, A, base, step, stream); break;
-      default: launch_tiles<PATH_INT8, 8, 0>(MODE, d, A, base, step, stream); break;
+      case 4: launch_tiles<PATH_INT8, 4, 0>(f.ty, MODE, d, A, base, step, stream); break;
+      case 5: launch_tiles<PATH_INT8, 5, 0>(f.ty, MODE, d, A, base, step, stream); break;
+      case 6: launch_tiles<PATH_INT8, 6, 0>(f.ty, MODE, d, A, base, step, stream); break;
+      case 7: launch_tiles<PATH_INT8, 7, 0>(f.ty, MODE, d, A, base, step, stream); break;
+      default: launch_tiles<PATH_INT8, 8, 0>(f.ty, MODE, d, A, base, step, stream); break;
     }
   } else if (f.precision == OVFEM_FP64_SF) {
     if (f.elem == OVFEM_ELEMENT_TRILINEAR)
-      launch_tiles<PATH_FP64SF, 8, 1>(MODE, d, A, base, step, stream);
+      launch_tiles<PATH_FP64SF, 8, 1>(f.ty, MODE, d, A, base, step, stream);
     else
-      launch_tiles<PATH_FP64SF, 8, 0>(MODE, d, A, base, step, stream);
+      launch_tiles<PATH_FP64SF, 8, 0>(f.ty, MODE, d, A, base, step, stream);
   } else {
-    launch_tiles<PATH_BF16, 8, 0>(MODE, d, A, base, step, stream);
+    launch_tiles<PATH_BF16, 8, 0>(f.ty, MODE, d, A, base, step, stream);
   }
   OVFEM_HIP(hipGetLastError());
 }
@@ -236,37 +237,38 @@ void launch_units(Form f, const KArgs* units, const int* begin, int n_units, int
   const bool d = f.damp;
   if (f.precision == OVFEM_FP64) {
     if (f.elem == OVFEM_ELEMENT_TRILINEAR)
-      launch_list<PATH_FP64, 8, 1>(d, grid, units, begin, n_units, total, base, step, stream);
+      launch_list<PATH_FP64, 8, 1>(f.ty, d, grid, units, begin, n_units, total, base, step, stream);
     else
-      launch_list<PATH_FP64, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+      launch_list<PATH_FP64, 8, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream);
   } else if (f.precision == OVFEM_INT8) {
     switch (f.stages) {
-      case 4: launch_list<PATH_INT8, 4, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
-      case 5: launch_list<PATH_INT8, 5, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
-      case 6: launch_list<PATH_INT8, 6, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
-      case 7: launch_list<PATH_INT8, 7, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
-      default: launch_list<PATH_INT8, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 4: launch_list<PATH_INT8, 4, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 5: launch_list<PATH_INT8, 5, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 6: launch_list<PATH_INT8, 6, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream); break;
+      case 7: launch_list<PATH_INT8, 7, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream); break;
+      default: launch_list<PATH_INT8, 8, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream); break;
     }
   } else if (f.precision == OVFEM_FP64_SF) {
     if (f.elem == OVFEM_ELEMENT_TRILINEAR)
-      launch_list<PATH_FP64SF, 8, 1>(d, grid, units, begin, n_units, total, base, step, stream);
+      launch_list<PATH_FP64SF, 8, 1>(f.ty, d, grid, units, begin, n_units, total, base, step, stream);
     else
-      launch_list<PATH_FP64SF, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+      launch_list<PATH_FP64SF, 8, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream);
   } else {
-    launch_list<PATH_BF16, 8, 0>(d, grid, units, begin, n_units, total, base, step, stream);
+    launch_list<PATH_BF16, 8, 0>(f.ty, d, grid, units, begin, n_units, total, base, step, stream);
   }
   OVFEM_HIP(hipGetLastError());
 }
 
 // Tiling: 15 x 15 owned node columns per work-group, node planes split into chunks of
 // equal depth close to chunk_planes.
-Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int chunk_planes) {
+Geom make_geom(int64_t nx, int64_t ny, int64_t nz, int chunk_planes, int ty) {
   Geom g{};
   g.nx = (int)nx;
   g.ny = (int)ny;
   g.nz = (int)nz;
+  g.ty = ty;
   g.tiles_x = (int)((nx + 1 + TN - 1) / TN);
-  g.tiles_y = (int)((ny + 1 + TN - 1) / TN);
+  g.tiles_y = (int)((ny + 1 + (ty - 1) - 1) / (ty - 1));
   const int64_t target = std::max(1, chunk_planes);
   g.chunks = (int)((nz + 1 + target - 1) / target);
   g.tz = (int)((nz + 1 + g.chunks - 1) / g.chunks);
@@ -364,8 +366,11 @@ struct ovfem_solver {
   int buf_cur(int ph) const { return ph; }
   int buf_prev(int ph) const { return damped() ? (ph + 2) % 3 : ph ^ 1; }
   int buf_next(int ph) const { return damped() ? (ph + 1) % 3 : ph ^ 1; }
-  Form form() const { return Form{precision, stages, damped(), element}; }
-  int form_code() const { return element * 256 + precision * 16 + (precision == OVFEM_INT8 ? stages : 0); }
+  Form form() const { return Form{precision, stages, damped(), element, geom.ty}; }
+  // kernels of this form: element, precision, stage count, tile height
+  int form_code() const {
+    return geom.ty * 4096 + element * 256 + precision * 16 + (precision == OVFEM_INT8 ? stages : 0);
+  }
   double damp_b() const { return beta / dt; }
   double damp_a() const { return 0.5 * alpha * dt; }
   // stability of the (damped) recursion for the largest mode: w^2 dt (dt + 2 beta) <= 4
@@ -396,7 +401,7 @@ struct ovfem_solver {
   static int tile_of(const Geom& g, int64_t node) {
     const int64_t X = node % (g.nx + 1), Y = (node / (g.nx + 1)) % (g.ny + 1),
                   Z = node / ((int64_t)(g.nx + 1) * (g.ny + 1));
-    return (int)(X / TN + g.tiles_x * (Y / TN + (int64_t)g.tiles_y * (Z / g.tz)));
+    return (int)(X / TN + g.tiles_x * (Y / (g.ty - 1) + (int64_t)g.tiles_y * (Z / g.tz)));
   }
 
   void refresh_acoef() {
@@ -612,8 +617,8 @@ struct ovfem_solver {
   }
 
   // change the z-chunk depth: new tiling and tile lists; the state is kept
-  void retile(int planes) {
-    const Geom g = make_geom(nx, ny, nz, planes);
+  void retile(int planes, int ty) {
+    const Geom g = make_geom(nx, ny, nz, planes, ty);
     SourceTables st;
     ReceiverTables rt;
     try {
@@ -717,7 +722,7 @@ struct ovfem_batch {
   double check_members() const {
     double items = 0;
     for (auto* m : members) {
-      require(m->form_code() == members[0]->form_code(), "ovfem_batch_step: members differ in precision or stages",
+      require(m->form_code() == members[0]->form_code(), "ovfem_batch_step: members differ in precision, stages or tile rows",
               OVFEM_ESTATE);
       require(m->damped() == members[0]->damped(),
               "ovfem_batch_step: damped and undamped members cannot share a batch", OVFEM_ESTATE);
@@ -844,7 +849,7 @@ ovfem_status ovfem_create(ovfem_solver** out, int64_t nx, int64_t ny, int64_t nz
       s->precision = precision;
       s->n_nodes = (size_t)(nx + 1) * (ny + 1) * (nz + 1);
       s->n_elem = (size_t)nx * ny * nz;
-      s->geom = make_geom(nx, ny, nz, s->chunk_planes);
+      s->geom = make_geom(nx, ny, nz, s->chunk_planes, 16);
       const Geom& g = s->geom;
       s->u[0].alloc((size_t)n_shots * s->vec());
       s->u[1].alloc((size_t)n_shots * s->vec());
@@ -1209,11 +1214,28 @@ ovfem_status ovfem_set_tuning(ovfem_solver* s, int32_t chunk_planes, int32_t per
     require(graph_steps >= 0 && graph_steps <= 4096 && graph_steps % 2 == 0,
             "ovfem_set_tuning: graph_steps must be even and in 0..4096");
     s->check_device();
-    if (make_geom(s->nx, s->ny, s->nz, chunk_planes).tz != s->geom.tz) s->retile(chunk_planes);
+    if (make_geom(s->nx, s->ny, s->nz, chunk_planes, s->geom.ty).tz != s->geom.tz)
+      s->retile(chunk_planes, s->geom.ty);
     s->chunk_planes = chunk_planes;
     s->persist_groups = persistent_groups;
     s->graph_steps = graph_steps;
     s->invalidate_launches();
+  });
+}
+
+ovfem_status ovfem_set_tile_rows(ovfem_solver* s, int32_t rows) {
+  return guarded([&] {
+    require(s != nullptr, "ovfem_set_tile_rows: solver is NULL");
+    require(rows == 16 || rows == 32, "ovfem_set_tile_rows: rows must be 16 or 32");
+    s->check_device();
+    if (rows != s->geom.ty) s->retile(s->chunk_planes, rows);
+  });
+}
+
+ovfem_status ovfem_get_tile_rows(ovfem_solver* s, int32_t* rows) {
+  return guarded([&] {
+    require(s != nullptr && rows != nullptr, "ovfem_get_tile_rows: NULL argument");
+    *rows = s->geom.ty;
   });
 }
 
@@ -1238,7 +1260,7 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const int64_t step0 = s->step;
     const int g0 = s->graph_steps;
-    int best_planes = s->chunk_planes, best_persist = s->persist_groups;
+    int best_planes = s->chunk_planes, best_persist = s->persist_groups, best_rows = s->geom.ty;
     double best = std::numeric_limits<double>::infinity();
     auto cleanup = [&] {
       if (e0) (void)hipEventDestroy(e0);
@@ -1273,12 +1295,13 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       }
       s->ckpt_valid = false;
       s->graph_steps = 0;  // plain launches for the tiling and grid choice
+      for (int rows : {16, 32}) {
       int last_tz = -1;
       for (int pl : plane_opts) {
-        const int tz = make_geom(s->nx, s->ny, s->nz, pl).tz;
+        const int tz = make_geom(s->nx, s->ny, s->nz, pl, rows).tz;
         if (tz == last_tz) continue;
         last_tz = tz;
-        s->retile(pl);
+        s->retile(pl, rows);
         for (int pg : persist_opts) {
           s->persist_groups = pg;
           s->invalidate_launches();
@@ -1293,10 +1316,12 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
             best = ms / steps;
             best_planes = pl;
             best_persist = pg;
+            best_rows = rows;
           }
         }
       }
-      s->retile(best_planes);
+      }
+      s->retile(best_planes, best_rows);
       s->persist_groups = best_persist;
       // captured blocks against plain launches, at the chosen tiling
       const int64_t gsteps = std::max<int64_t>(64, ((int64_t)steps + 63) / 64 * 64);

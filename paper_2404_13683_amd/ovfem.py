@@ -50,6 +50,8 @@ SIGNATURES = {
     "ovfem_set_tuning": (_i32, [_vp, _i32, _i32, _i32]),
     "ovfem_get_tuning": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "ovfem_autotune": (_i32, [_vp, _i32, ctypes.POINTER(_f64)]),
+    "ovfem_set_tile_rows": (_i32, [_vp, _i32]),
+    "ovfem_get_tile_rows": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "ovfem_batch_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32]),
     "ovfem_batch_destroy": (_i32, [_vp]),
     "ovfem_batch_set_tuning": (_i32, [_vp, _i32]),
@@ -333,14 +335,17 @@ class Solver:
         return v.value
 
     # --- launch configuration
-    def set_tuning(self, chunk_planes=16, persistent_groups=0, graph_steps=0):
+    def set_tuning(self, chunk_planes=16, persistent_groups=0, graph_steps=0, tile_rows=None):
         self._touch()
+        if tile_rows is not None:
+            _check(_LIB.ovfem_set_tile_rows(self._h, int(tile_rows)))
         _check(_LIB.ovfem_set_tuning(self._h, int(chunk_planes), int(persistent_groups), int(graph_steps)))
 
     def get_tuning(self):
-        a, b, c = _i32(), _i32(), _i32()
+        a, b, c, r = _i32(), _i32(), _i32(), _i32()
         _check(_LIB.ovfem_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"chunk_planes": a.value, "persistent_groups": b.value, "graph_steps": c.value}
+        _check(_LIB.ovfem_get_tile_rows(self._h, ctypes.byref(r)))
+        return {"chunk_planes": a.value, "persistent_groups": b.value, "graph_steps": c.value, "tile_rows": r.value}
 
     def autotune(self, steps=20):
         """Pick the fastest launch configuration; returns its ms per step."""

@@ -22,10 +22,12 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
 
 
-def _solver(w, prec, **tuning):
+def _solver(w, prec, tile_rows=None, **tuning):
     from paper_2404_13683_amd.ovfem import Solver
     s = Solver.from_workload(w, precision=prec)
-    if tuning:
+    if tile_rows is not None:
+        s.set_tuning(**dict(s.get_tuning(), tile_rows=tile_rows, **tuning))
+    elif tuning:
         s.set_tuning(**tuning)
     return s
 
@@ -182,6 +184,58 @@ def test_chunk_depth(prec):
     if prec == "fp64":
         for planes in got:
             assert np.array_equal(got[planes], got[16])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tile_rows(prec):
+    """Tiles of 16 x 32 elements (512 threads) against the default 16 x 16: FP64 bitwise (the
+    same element products and two-term node sums), INT8 within the trace bound of the oracle
+    (its staging exponent spans the tile's staged block); ragged grids, matvec, and a damped
+    run; a batch of members with 32-row tiles is bitwise its members stepped alone."""
+    import torch
+
+    from paper_2404_13683_amd.ovfem import Batch
+    w = wl.layered_c2(nx=37, ny=70, nz=23, nt=80, seed=35)  # 71 node rows: 3 tiles of 31, 5 of 15
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    ref, _, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    u = torch.from_numpy(np.random.default_rng(3).standard_normal(3 * w.n_nodes)).cuda()
+    ku_ref = oasm.matvec(u.cpu().numpy().reshape(m.node_shape), w.lam, w.mu, w.h).reshape(-1)
+    out = {}
+    for rows in (16, 32):
+        s = _solver(w, prec, chunk_planes=9, tile_rows=rows)
+        assert s.get_tuning()["tile_rows"] == rows
+        s.step(w.nt)
+        tr = s.get_traces().cpu().numpy()[0]
+        ku = s.matvec(u).cpu().numpy()
+        out[rows] = (tr, ku, s.get_wavefield(0).cpu().numpy())
+        s.close()
+        err, merr = _rel(tr, ref), _rel(ku, ku_ref)
+        print("%s tile rows %d: traces vs oracle %.3e, matvec %.3e" % (prec, rows, err, merr))
+        assert err <= TRACE_TOL and merr <= 1e-12
+    if prec.startswith("fp64"):
+        for a, b in zip(out[16], out[32]):
+            assert np.array_equal(a, b)
+    # damped, and a batch of 32-row members against stepping alone
+    d1 = wl.layered_c2(nx=20, ny=40, nz=12, nt=40, seed=36)
+    d2 = wl.layered_c2(nx=33, ny=17, nz=10, nt=40, seed=37)
+    alone = [_solver(d, prec, tile_rows=32) for d in (d1, d2)]
+    members = [_solver(d, prec, tile_rows=32) for d in (d1, d2)]
+    for x in alone + members:
+        x.set_damping(3.0, 2e-4 * d1.dt)
+    b = Batch(members)
+    b.step(40)
+    b.close()
+    for a, mm in zip(alone, members):
+        a.step(40)
+        _same(_state(mm), _state(a))
+
+
+def test_batch_rejects_mixed_tile_rows():
+    from paper_2404_13683_amd.ovfem import Batch, OvfemError
+    d = wl.uneven_domains_c3(n_domains=2, smallest=(8, 8, 8), largest=(12, 10, 9), nt=10, n_rec=2)
+    b = Batch([_solver(d[0], "fp64", tile_rows=16), _solver(d[1], "fp64", tile_rows=32)])
+    with pytest.raises(OvfemError, match="tile rows"):
+        b.step(1)
 
 
 @pytest.mark.parametrize("n_shots", [1, 4])
