@@ -308,8 +308,8 @@ ovfem_status ovfem_batch_step(ovfem_batch* b, int64_t n);
  * that the library holds on every device it runs on until the process ends, instead of
  * device buffers it allocates.  It calls no hipMalloc or hipFree.  Results are those of
  * ovfem_batch_step (bitwise: the same kernels on the same tables); asynchronous likewise.
- * The tables take 6 * 240 + 4 bytes per unit (a unit is one shot of one member) plus 4:
- * EINVAL beyond OVFEM_NOALLOC_SCRATCH_BYTES (726 units).  ESTATE unless every member has
+ * The tables take 6 * 248 + 4 bytes per unit (a unit is one shot of one member) plus 4:
+ * EINVAL beyond OVFEM_NOALLOC_SCRATCH_BYTES (702 units).  ESTATE unless every member has
  * model and dt set and has stepped since its model, fixed nodes, dt or damping last
  * changed (ovfem_step(member, 0) suffices: it builds the member's dt^2/m table).
  * Every call on one device writes the same array: calls on one stream are ordered, calls

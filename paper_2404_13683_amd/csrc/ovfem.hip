@@ -794,6 +794,8 @@ struct ovfem_batch {
 // per device, held until the process ends.  Host code must not pass its name to a kernel
 // or a copy (it is a host-side stand-in); scratch_address() gives each device's address.
 static __device__ __align__(256) unsigned char scratch[OVFEM_NOALLOC_SCRATCH_BYTES];
+static_assert((OVFEM_NOALLOC_SCRATCH_BYTES - sizeof(int)) / (kBatchTables * sizeof(KArgs) + sizeof(int)) == 702,
+              "ovfem.h states the unit limit of ovfem_batch_step_noalloc");
 
 namespace {
 std::mutex g_scratch_mutex;

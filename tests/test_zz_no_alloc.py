@@ -88,7 +88,7 @@ def test_noalloc_batch_step_refuses_what_it_cannot_hold():
     assert m.get_step() == 2
     b.close()
     m.close()
-    many = wl.shots_c3(nx=40, ny=40, nz=4, n_shots=800, nt=4, n_rec=1, seed=9)  # 800 units > 726
+    many = wl.shots_c3(nx=40, ny=40, nz=4, n_shots=800, nt=4, n_rec=1, seed=9)  # 800 units > 702
     s = Solver.from_workload(many, precision="fp64")
     s.step(0)
     b = Batch([s])
