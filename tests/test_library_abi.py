@@ -64,7 +64,13 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert lib.ovfem_batch_create(ctypes.byref(b), members, 1) == -1
     assert b"NULL member" in lib.ovfem_last_error()
     assert lib.ovfem_batch_step(None, 1) == -1
+    assert lib.ovfem_batch_step_noalloc(None, 1) == -1
+    assert b"batch is NULL" in lib.ovfem_last_error()
     assert lib.ovfem_batch_set_tuning(None, 0) == -1
+    assert lib.ovfem_batch_set_graph(None, 6) == -1
+    assert lib.ovfem_set_tile_rows(None, 16) == -1
+    r = ctypes.c_int32()
+    assert lib.ovfem_get_tile_rows(None, ctypes.byref(r)) == -1
     assert lib.ovfem_batch_destroy(None) == 0
     assert lib.ovfem_version() >= 200
 
