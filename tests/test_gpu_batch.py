@@ -158,6 +158,24 @@ def test_uneven_batch_replayed_from_captured_graphs(prec):
     assert graph[2].get_step() == 110 and graph[0].get_step() == 107
 
 
+def test_damped_batch_with_graph_steps_launches_plainly():
+    """Damped batches are not captured: with graph steps set they step as plain launches,
+    bitwise equal to their members stepped alone."""
+    from paper_2404_13683_amd.ovfem import Batch
+    doms = wl.uneven_domains_c3(n_domains=2, smallest=(10, 9, 8), largest=(21, 18, 12), nt=40, n_rec=3, seed=13)
+    alone = [_solver(d, "int8") for d in doms]
+    members = [_solver(d, "int8") for d in doms]
+    for x in alone + members:
+        x.set_damping(2.0, 1e-4 * doms[0].dt)
+    b = Batch(members)
+    b.set_graph(12)
+    b.step(31)
+    b.close()
+    for a, m in zip(alone, members):
+        a.step(31)
+        _same(_state(m), _state(a))
+
+
 def test_batch_rejects_mixed_precision():
     from paper_2404_13683_amd.ovfem import Batch, OvfemError
     d = wl.uneven_domains_c3(n_domains=2, smallest=(8, 8, 8), largest=(12, 10, 9), nt=10, n_rec=2)
