@@ -455,7 +455,8 @@ def main():
     rec_nt = max(nt_timed, full)
     wls, desc, batched = make_workload(args.workload, rec_nt)
     free_dof = sum(w.free_dof() * w.n_shots for w in wls)
-    n_elem = sum(w.n_elements * w.n_shots for w in wls)
+    # solid voxels (the useful element products; removed voxels are computed as zeros)
+    n_elem = sum((w.n_elements if w.solid is None else int(np.count_nonzero(w.solid))) * w.n_shots for w in wls)
     bytes_step = sum(algorithmic_bytes(w) for w in wls)
     paths = args.paths.split(",")
     runs, res = {}, {}
