@@ -224,12 +224,12 @@ ovfem_status ovfem_set_element(ovfem_solver* s, int32_t element);
  * negative or non-finite values, or a dt already set that the new beta makes unstable. */
 ovfem_status ovfem_set_damping(ovfem_solver* s, double alpha, double beta);
 
-/* Digit stages M (4..8, default 8) of OVFEM_INT8: u is split under the tile exponent E
- * into q = floor(u 2^(8M-2-E)), |q| < 2^(8M-2), written as M balanced base-256 digits
- * (Sec. 2, Eqs. (16)-(17); the paper's Table 3 compares stage counts).  Fewer stages
- * mean fewer matrix-core products and recombination steps at lower accuracy: about
- * 8M - 2 bits relative to the largest value of the 27 neighbouring tiles (M = 4 is
- * about FP32, M = 8 at least FP64).  OVFEM_INT8_BF16 runs M = 8 only (EINVAL otherwise);
+/* Digit stages M (4..8, default 8) of OVFEM_INT8: u is split under the staging exponent S
+ * of its element layer into q = rint(u 2^(8M-2-S)), |q| <= 2^(8M-2), written as M balanced
+ * base-256 digits (Sec. 2, Eqs. (16)-(17); the paper's Table 3 compares stage counts).
+ * Fewer stages mean fewer matrix-core products and recombination steps at lower accuracy:
+ * about 8M - 2 bits relative to the largest of the 17 x 17 x 2 nodes a work-group stages
+ * for that layer (M = 4 is about FP32, M = 8 at least FP64).  OVFEM_INT8_BF16 runs M = 8 only (EINVAL otherwise);
  * OVFEM_FP64 ignores the setting. */
 ovfem_status ovfem_set_stages(ovfem_solver* s, int32_t stages);
 
@@ -242,10 +242,11 @@ ovfem_status ovfem_get_stages(ovfem_solver* s, int32_t* stages);
  * grid, rounded down to a multiple of 8 (0 = one work-group per tile and shot).
  * graph_steps (even, 0..4096; default 0 = never): ovfem_step calls of at least that many
  * steps replay a captured HIP graph of graph_steps steps instead of launching each step
- * (graphs are not used while checkpointing for the adjoint).  The FP64 path
- * gives bitwise-identical results under every setting; the INT8 forms take their
- * per-tile exponents over the tiling, so chunk_planes can change their last bits (their
- * accuracy bound does not change).  Keeps the wavefield state; a changed tiling
+ * (graphs are not used while checkpointing for the adjoint).  Every path gives
+ * bitwise-identical results under every setting here (the INT8 staging exponent depends
+ * only on the nodes staged for one element layer, not on the chunk depth); only the tile
+ * height of ovfem_set_tile_rows changes which nodes a work-group stages together, and with
+ * it the last bits of the INT8 forms (their accuracy bound does not change).  Keeps the wavefield state; a changed tiling
  * invalidates a checkpointed forward run.  EINVAL for out-of-range values. */
 ovfem_status ovfem_set_tuning(ovfem_solver* s, int32_t chunk_planes, int32_t persistent_groups,
                               int32_t graph_steps);

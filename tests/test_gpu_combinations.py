@@ -138,9 +138,10 @@ def test_adjoint_combinations(case):
 
 
 def test_precision_switches_mid_run():
-    """Every step writes its tile exponents whatever the path, so the precision (and the
-    stage count) can change between steps: a run that switches fp64 -> int8 (M = 6) ->
-    fp64-sf -> int8-bf16 -> int8 matches the oracle's run."""
+    """The INT8 staging exponent comes from the values each step stages, and every path
+    reads and writes the same wavefield buffers, so the precision (and the stage count) can
+    change between steps: a run that switches fp64 -> int8 (M = 6) -> fp64-sf -> int8-bf16 ->
+    int8 matches the oracle's run."""
     from paper_2404_13683_amd.ovfem import Solver
     w = wl.layered_c2(nx=24, ny=20, nz=16, f0=30.0, nt=200, seed=85)
     m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)

@@ -2,7 +2,7 @@
 
 The paper compares INT8 results with M = 4..8 stages against FP128/FP64/FP32: accuracy
 grows with M, M = 4 is about FP32 and M = 8 at least FP64.  Here q carries 8M - 2 bits
-under the tile exponent, and the same ordering is checked against the exact K u.
+under the staging exponent of its element layer, and the same ordering is checked against the exact K u.
 """
 from fractions import Fraction
 
