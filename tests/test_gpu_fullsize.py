@@ -149,6 +149,29 @@ def test_c5_topography_512x512x256_4000_steps():
 
 
 @pytest.mark.timeout(600)
+def test_c5_slab_512x512x32_4000_steps_both_tile_heights():
+    """The 512 x 512 x 32 slab of the topography recipe (one GPU's share of the large model
+    split eight ways along z), where the tuner prefers the 16 x 32-element tiles: both tile
+    heights against the oracle at sampled nodes, and against the FP64 path over all steps."""
+    from paper_2404_13683_amd.ovfem import Solver
+    w = wl.topography_c5(nz=32)
+    out = run_pair(w, w.nt, check_state_after=True)
+    for rows, planes in ((32, 12), (16, 32)):
+        s = Solver.from_workload(w, precision="int8", receivers_nt=w.nt + 1)
+        s.set_tuning(chunk_planes=planes, tile_rows=rows)
+        assert s.get_tuning()["tile_rows"] == rows
+        check_matvec_sampled(w, s, "int8 rows=%d" % rows)
+        s.reset()
+        s.step(w.nt)
+        tr = s.get_traces().cpu().numpy()[..., :w.nt]
+        err = _rel(tr, out["fp64"])
+        print("%s int8 tile rows %d, %d planes vs FP64 traces: rel L2 %.3e" % (w.name, rows, planes, err))
+        assert err <= TRACE_TOL
+        check_one_step_sampled(w, s, "int8 rows=%d" % rows)
+        s.close()
+
+
+@pytest.mark.timeout(600)
 def test_c3_64_shots_128x128x64_1000_steps():
     """All 64 shots in one solver; two of them against one-shot solvers (bitwise) and
     against the oracle's update at sampled nodes."""
