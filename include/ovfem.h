@@ -269,7 +269,9 @@ ovfem_status ovfem_get_tile_rows(ovfem_solver* s, int32_t* rows);
  * sources and precision for each tile height (16 and 32 element rows) and candidate chunk
  * depth (8, 12, 16, 24, 32, 48, 64, 96 planes, each evened out over the chunks it gives)
  * and, for n_shots > 1, grid caps of
- * 0, 2 and 4 work-groups per compute unit, keeps the fastest, then times graph_steps 0
+ * 0, 2 and 4 work-groups per compute unit, in two passes over all candidates, and keeps
+ * the candidate with the fastest of its two times (the first pass also raises the clocks,
+ * which would otherwise favour the candidates timed last); it then times graph_steps 0
  * and 64 at that setting and keeps the faster.  The wavefield pair, traces and step counter are
  * restored afterwards; a checkpointed forward run is invalidated.  best_ms_per_step
  * (HOST, nullable) receives the best time per step in milliseconds.  Synchronises the

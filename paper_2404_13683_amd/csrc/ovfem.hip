@@ -1297,15 +1297,26 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
       }
       s->ckpt_valid = false;
       s->graph_steps = 0;  // plain launches for the tiling and grid choice
+      struct Candidate {
+        int rows, planes, persist;
+        double ms;
+      };
+      std::vector<Candidate> cands;
       for (int rows : {16, 32}) {
-      int last_tz = -1;
-      for (int pl : plane_opts) {
-        const int tz = make_geom(s->nx, s->ny, s->nz, pl, rows).tz;
-        if (tz == last_tz) continue;
-        last_tz = tz;
-        s->retile(pl, rows);
-        for (int pg : persist_opts) {
-          s->persist_groups = pg;
+        int last_tz = -1;
+        for (int pl : plane_opts) {
+          const int tz = make_geom(s->nx, s->ny, s->nz, pl, rows).tz;
+          if (tz == last_tz) continue;
+          last_tz = tz;
+          for (int pg : persist_opts) cands.push_back({rows, pl, pg, std::numeric_limits<double>::infinity()});
+        }
+      }
+      // two passes, each candidate keeping its faster time: the first pass also brings the
+      // clocks up, which would otherwise favour whichever candidates run last
+      for (int pass = 0; pass < 2; ++pass) {
+        for (Candidate& c : cands) {
+          if (s->chunk_planes != c.planes || s->geom.ty != c.rows) s->retile(c.planes, c.rows);
+          s->persist_groups = c.persist;
           s->invalidate_launches();
           s->do_steps(2);  // warm-up: tables, caches
           OVFEM_HIP(hipEventRecord(e0, s->stream));
@@ -1314,15 +1325,16 @@ ovfem_status ovfem_autotune(ovfem_solver* s, int32_t steps, double* best_ms_per_
           OVFEM_HIP(hipEventSynchronize(e1));
           float ms = 0;
           OVFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (ms / steps < best) {
-            best = ms / steps;
-            best_planes = pl;
-            best_persist = pg;
-            best_rows = rows;
-          }
+          c.ms = std::min(c.ms, (double)ms / steps);
         }
       }
-      }
+      for (const Candidate& c : cands)
+        if (c.ms < best) {
+          best = c.ms;
+          best_planes = c.planes;
+          best_persist = c.persist;
+          best_rows = c.rows;
+        }
       s->retile(best_planes, best_rows);
       s->persist_groups = best_persist;
       // captured blocks against plain launches, at the chosen tiling
