@@ -21,7 +21,8 @@ Other workloads (parity cases, one JSON line each, not the headline):
   --workload c3-shots    64 shots on 128 x 128 x 64 in one launch per step
   --workload c3-uneven   16 layered domains of uneven size, one batched launch per step
   --workload c5-slab     512 x 512 x 32 of the c5 recipe: one GPU's share of c5 split 8 ways
-  --workload c4-adjoint  96^3 misfit gradient: forward run with checkpoints every 50 steps, then
+  --workload c4-adjoint  96^3 misfit gradient: forward run with checkpoints every 50 steps (or
+                         --ckpt-every N; 1 keeps every state and needs no recompute), then
                          the discrete adjoint (recompute + backward step + gradient terms) per path,
                          gradients checked against the stored full-length oracle adjoint
 
@@ -321,7 +322,7 @@ def cpu_sample(name, wls):
 
 def adjoint_bench(args):
     """The 96^3 misfit gradient on each path: the forward run from rest with checkpoints
-    every 50 steps, then the discrete adjoint, each timed with HIP events on the solver's
+    every 50 steps (--ckpt-every), then the discrete adjoint, each timed with HIP events on the solver's
     stream; gradients at the stored voxels against the oracle's full-length adjoint."""
     import torch
 
@@ -329,7 +330,7 @@ def adjoint_bench(args):
     from paper_2404_13683_amd.ovfem import Solver
     fx = json.load(open(C4_ORACLE))
     true, start = workloads.adjoint_c4()
-    nt, every = start.nt, fx["ckpt_every"]
+    nt, every = start.nt, (args.ckpt_every or fx["ckpt_every"])
     s = Solver.from_workload(true, precision="fp64")
     s.step(nt)
     d_obs = s.get_traces().clone()
@@ -430,6 +431,9 @@ def main():
     ap.add_argument("--stage-sweep", action="store_true",
                     help="also time the INT8 path with 4..7 digit stages (accuracy/speed trade, Table 3)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
+    ap.add_argument("--ckpt-every", type=int, default=0,
+                    help="c4-adjoint: checkpoint interval (default: the stored oracle run's, 50; 1 keeps every "
+                         "state and needs no recompute)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)

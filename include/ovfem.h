@@ -195,8 +195,9 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
  * entries t >= N are ignored), e.g. traces - observed for J = 1/2 |traces - observed|^2.
  * g_lam, g_mu: DEVICE float64 arrays of nx*ny*nz, overwritten (0 for removed voxels).
  * Each checkpoint segment is recomputed forward (bitwise identical: the kernels are
- * deterministic) and then stepped backward; the adjoint steps use the solver's
- * precision for K.  The wavefield state and traces of the forward run are unchanged.
+ * deterministic; every - 1 steps per segment, none with every = 1, which trades two
+ * stored nodal vectors per step for the recompute) and then stepped backward; the
+ * adjoint steps use the solver's precision for K.  The wavefield state and traces of the forward run are unchanged.
  * Synchronises the stream.  ESTATE if the preconditions do not hold. */
 ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_lam, double* g_mu);
 

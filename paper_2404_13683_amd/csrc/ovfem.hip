@@ -1468,13 +1468,16 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
 
       for (int64_t sg = (n - 1) / every; sg >= 0; --sg) {
         const int64_t s0 = sg * every, e0 = std::min(s0 + every, n);
-        // state(k) = u^{s0+k}: u^{s0} and u^{s0-1} from the checkpoint, the rest recomputed
+        // state(k) = u^{s0+k}: u^{s0} and u^{s0-1} from the checkpoint, the rest recomputed.
+        // The adjoint steps m = e0 .. s0+1 read u^{m-1} (and u^{m-2} when damped), so the
+        // segment needs u^{s0-1} .. u^{e0-1}: e0 - s0 - 1 recomputed steps (none when every
+        // step is checkpointed)
         auto state = [&](int64_t k) -> double* {
           if (k < 0) return s->ckpt_u(sg, 1);
           if (k == 0) return s->ckpt_u(sg, 0);
           return seg.p + (size_t)k * vec;
         };
-        for (int64_t t = s0; t < e0; ++t) {
+        for (int64_t t = s0; t + 1 < e0; ++t) {
           F.u = state(t - s0);
           F.uprev = state(t - s0 - 1);
           F.unext = state(t - s0 + 1);
