@@ -174,7 +174,9 @@ ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step);
 /* Checkpointing of forward runs for ovfem_adjoint: allocates room for max_steps steps
  * and, from now on, stores (u^s, u^{s-1}) on the device at every step s that is a
  * multiple of `every` (counted from reset).  every = 0 disables it.  Resets the
- * wavefield (as ovfem_reset).  Device memory: 2 (max_steps / every + 1) nodal vectors.
+ * wavefield (as ovfem_reset).  Device memory: 2 (max_steps / every + 1) nodal vectors;
+ * with every = 1, max_steps + 2: the forward run then writes each new state straight
+ * into its slot of one tape u^{-1}, u^0, ..., and the adjoint recomputes nothing.
  * EINVAL with every > 0 on a solver of more than one shot; ENOMEM if it does not fit. */
 ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max_steps);
 

@@ -377,7 +377,13 @@ struct ovfem_solver {
   double dt_limit(double b) const {
     return wmax2 > 0 ? -b + std::sqrt(b * b + 4.0 / wmax2) : std::numeric_limits<double>::infinity();
   }
-  double* ckpt_u(int64_t slot, int which) { return ckpt.p + (size_t)(2 * slot + which) * vec(); }
+  // u^{slot every} (which = 0) or u^{slot every - 1} (which = 1) of the checkpoint store.
+  // every > 1: pairs [slot][which]; every = 1: one tape of states u^{-1}, u^0, u^1, ...
+  // that the forward run steps through directly (no copies)
+  double* ckpt_u(int64_t slot, int which) {
+    if (ckpt_every == 1) return ckpt.p + (size_t)(slot + 1 - which) * vec();
+    return ckpt.p + (size_t)(2 * slot + which) * vec();
+  }
 
   void check_device() {
     int d = -1;
@@ -598,6 +604,31 @@ struct ovfem_solver {
       OVFEM_HIP(hipStreamSynchronize(stream));  // s0 is a host stack value
       for (; done + graph_steps <= n; done += graph_steps) OVFEM_HIP(hipGraphLaunch(graph[phase], stream));
       step += done;  // an even count: the phase is unchanged
+    }
+    if (ckpt_valid && ckpt_every == 1 && n_shots == 1) {
+      // every state kept: step through the tape, u^{s+1} written straight to its slot
+      const int64_t m = std::min<int64_t>(n - done, ckpt_slots - 1 - step);
+      if (m > 0) {
+        const size_t bytes = vec() * sizeof(double);
+        OVFEM_HIP(hipMemcpyAsync(ckpt_u(step, 0), u[buf_cur(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
+        OVFEM_HIP(hipMemcpyAsync(ckpt_u(step, 1), u[buf_prev(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
+        for (int64_t i = 0; i < m; ++i) {
+          KArgs A = shot_args(0, phase);
+          A.u = ckpt_u(step, 0);
+          A.uprev = ckpt_u(step, 1);
+          A.unext = ckpt_u(step + 1, 0);
+          A.n_units = 1;
+          A.unit_u = (long long)vec();
+          A.unit_src = geom.n_wg + 1;
+          A.unit_tr = (long long)n_rec * 3 * rec_nt;
+          launch_unit<MODE_STEP>(form(), A, nullptr, step, stream);
+          phase = buf_next(phase);
+          ++step;
+        }
+        done += m;
+        OVFEM_HIP(hipMemcpyAsync(u[buf_cur(phase)].p, ckpt_u(step, 0), bytes, hipMemcpyDeviceToDevice, stream));
+        OVFEM_HIP(hipMemcpyAsync(u[buf_prev(phase)].p, ckpt_u(step, 1), bytes, hipMemcpyDeviceToDevice, stream));
+      }
     }
     for (; done < n; ++done) {
       if (ckpt_valid && step % ckpt_every == 0) {
@@ -1388,7 +1419,8 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
     int64_t slots = 0;
     if (every > 0) {
       slots = max_steps / every + 1;
-      buf.alloc((size_t)slots * 2 * s->vec());
+      // every = 1: the tape u^{-1} .. u^{max_steps}; otherwise a (u^s, u^{s-1}) pair per slot
+      buf.alloc((size_t)(every == 1 ? slots + 1 : slots * 2) * s->vec());
     }
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     std::swap(s->ckpt, buf);

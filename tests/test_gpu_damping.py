@@ -196,6 +196,16 @@ def test_damped_adjoint_matches_the_oracle(prec):
           % (prec, el_, em_, _rel(gl_ref, gl_und)))
     assert el_ <= TRACE_TOL and em_ <= TRACE_TOL
     assert _rel(gl_ref, gl_und) > 1e-3
+    # every state kept (the forward run steps through its checkpoint store, three damped
+    # states apart), in two calls: the same traces, final state and gradient, bitwise
+    tr9, u9 = s.get_traces().cpu().numpy(), s.get_wavefield(0).cpu().numpy()
+    s.set_checkpointing(1, w.nt)
+    s.step(w.nt // 3)
+    s.step(w.nt - w.nt // 3)
+    assert np.array_equal(s.get_traces().cpu().numpy(), tr9)
+    assert np.array_equal(s.get_wavefield(0).cpu().numpy(), u9)
+    g1_lam, g1_mu = (g.cpu().numpy() for g in s.adjoint(res))
+    assert np.array_equal(g1_lam, g_lam) and np.array_equal(g1_mu, g_mu)
 
 
 def test_damped_autograd_and_central_differences():
