@@ -55,7 +55,7 @@ constexpr int TN = TE - 1;    // owned node columns per tile side
 constexpr int PN = TE + 1;    // node columns per staged plane side
 constexpr int NTHR = 256;     // threads per work-group of the one-element-per-thread kernels
 constexpr int NPAIR = 4;      // digit pairs (M = 8 digits)
-constexpr int QBITS = 62;     // fraction bits of q under the tile exponent
+constexpr int QBITS = 62;     // fraction bits of q under the staging exponent
 constexpr int NODE_DW = 16;   // dwords of one staged node: 4 pairs x (hi, lo) x 2 dwords
 // digit plane layout [row q][pair p][hi/lo][column x][2 dwords]: the B operand of a
 // lane (its element's nodes x and x+1 in one row) is 16 contiguous bytes
@@ -296,11 +296,21 @@ __device__ inline void stage_digits_i8(const D3& u, int S, uint32_t* dst) {
     lo[c] = (uint32_t)d ^ 0x80808080u;              // bytes d_j (two's complement)
     hi[c] = (uint32_t)(d >> 32) ^ 0x80808080u;
   }
+  // digits j, j+1 (bytes sel, sel+1 of one word) from one gather of the c0, c1 bytes:
+  // t = (c0 byte sel, c1 byte sel, c0 byte sel+1, c1 byte sel+1), then per digit
+  // (t bytes, c2 byte, 0): three byte permutes per two digits
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
+  for (int j = 0; j + 1 < M; j += 2) {
     const uint32_t* s = j < 4 ? lo : hi;
-    const int sel = j & 3;
-    // bytes: c0 byte sel, c1 byte sel, c2 byte sel, 0
+    const uint32_t sel = j & 3;
+    const uint32_t t = __builtin_amdgcn_perm(s[1], s[0], sel | (sel + 4) << 8 | (sel + 1) << 16 | (sel + 5) << 24);
+    dst[j * PN] = __builtin_amdgcn_perm(s[2], t, 0x0c000100u | (sel + 4) << 16);
+    dst[(j + 1) * PN] = __builtin_amdgcn_perm(s[2], t, 0x0c000302u | (sel + 5) << 16);
+  }
+  if constexpr (M % 2 == 1) {  // the last digit alone: (c0, c1, c2 byte sel, 0)
+    constexpr int j = M - 1;
+    const uint32_t* s = j < 4 ? lo : hi;
+    constexpr uint32_t sel = j & 3;
     const uint32_t t01 = __builtin_amdgcn_perm(s[1], s[0], 0x0c0c0400u | (sel << 8) | sel);
     dst[j * PN] = __builtin_amdgcn_perm(s[2], t01, 0x0c040100u | (sel << 16));
   }
@@ -995,79 +1005,6 @@ __global__ void __launch_bounds__(Tile<TY>::THREADS, is_f64_path(PATH) || TY == 
 // Adds n to the device step base (last node of a captured block of steps).
 static __global__ void ovfem_advance_step_kernel(long long* step_base, long long n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n;
-}
-
-// The two energies w^T K_lam u and w^T K_mu u of one element (h = 1) in the
-// sum-factorised form of sf_component: with W, Wh the Walsh coefficients of u and w
-// (sf_transform) and f_b = (1/16) q^|b| (q = 3/4 OVFEM, 1/3 trilinear),
-//     w^T K_lam u = sum_b f_b tr_b(u) tr_b(w),
-//     w^T K_mu u  = sum_b f_b sum_{j not in b} sum_c Wh_c[b+{j}] (W_c[b+{j}] + [c not in b] W_j[b+{c}]),
-// since w^T y = sum_{c,S} Wh_c[S] V_c[S] for y_{alpha,c} = sum_S chi_S(alpha) V_c[S].
-template <int ELEM>
-__device__ inline void sf_energies(const double W[3][8], const double tr[7], const double Wh[3][8],
-                                   const double trh[7], double& el, double& em) {
-  constexpr double q = ELEM == 1 ? 1.0 / 3.0 : 0.75;
-  const double f[3] = {1.0 / 16.0, q / 16.0, q * q / 16.0};
-  el = 0.0;
-  em = 0.0;
-#pragma unroll
-  for (int ib = 0; ib < 7; ++ib) {
-    const int b = kSfB[ib];
-    const int nb = (b & 1) + ((b >> 1) & 1) + ((b >> 2) & 1);
-    double sm = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      if ((b >> j) & 1) continue;
-      const int S = b | (1 << j);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double g = W[c][S];
-        if (!((b >> c) & 1)) g += W[j][b | (1 << c)];
-        sm = fma(Wh[c][S], g, sm);
-      }
-    }
-    el = fma(f[nb] * tr[ib], trh[ib], el);
-    em = fma(f[nb], sm, em);
-  }
-}
-
-// Per-element gradient terms of the discrete adjoint: for every solid element e,
-//     g_lam[e] -= h w_e^T K_lam u_e,   g_mu[e] -= h w_e^T K_mu u_e,
-// with u = u^{m-1} (with Rayleigh damping the staged (1+b) u^{m-1} - b u^{m-2}, b = beta/dt)
-// and w = w^m (the derivative of w^T K u with respect to lam_e, mu_e,
-// from K_e = h (lam_e K_lam + mu_e K_mu)).  The energies are formed sum-factorised
-// (sf_energies: about 300 flops per element instead of the 2304 of two dense 24 x 24
-// products).  One thread per element; each element's sums are private, so the
-// accumulation order is fixed.  ELEM: 0 OVFEM, 1 trilinear.
-template <int ELEM>
-__global__ void __launch_bounds__(NTHR) ovfem_gradient_kernel(Geom g, double h, const double* mat,
-                                                               const double* u, const double* u2, double b,
-                                                               const double* w, double* g_lam, double* g_mu) {
-  const long long e = (long long)blockIdx.x * NTHR + threadIdx.x;
-  const long long ne = (long long)g.nx * g.ny * g.nz;
-  if (e >= ne) return;
-  const double2 m = reinterpret_cast<const double2*>(mat)[e];
-  if (m.x == 0.0 && m.y == 0.0) return;  // removed voxel
-  const int X = (int)(e % g.nx), Y = (int)((e / g.nx) % g.ny), Z = (int)(e / ((long long)g.nx * g.ny));
-  double ue[24], we[24];
-#pragma unroll
-  for (int alpha = 0; alpha < 8; ++alpha) {
-    const long long n = (long long)(X + (alpha & 1)) +
-                        (long long)(g.nx + 1) * ((Y + ((alpha >> 1) & 1)) + (long long)(g.ny + 1) * (Z + (alpha >> 2)));
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double x = u[3 * n + c];
-      ue[3 * alpha + c] = u2 ? fma(b, x - u2[3 * n + c], x) : x;  // damped: the staged (1+b) u - b u2
-      we[3 * alpha + c] = w[3 * n + c];
-    }
-  }
-  double Wu[3][8], tru[7], Ww[3][8], trw[7];
-  sf_transform(ue, Wu, tru);
-  sf_transform(we, Ww, trw);
-  double gl, gm;
-  sf_energies<ELEM>(Wu, tru, Ww, trw, gl, gm);
-  g_lam[e] -= h * gl;
-  g_mu[e] -= h * gm;
 }
 
 }  // namespace ovfem

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "launch.hpp"
 #include "ovfem.h"
 
@@ -1496,7 +1497,28 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       B.src_row = d_arow.p;
       B.wavelet = residual;
       B.src_nt = s->rec_nt;
-      const int gblocks = (int)((s->n_elem + NTHR - 1) / NTHR);
+      // gradient terms: 16 x 16-element tiles by chunks of zc element layers (at least 4,
+      // so that a chunk's extra staged plane costs at most a quarter; deeper while the grid
+      // still has 2048 work-groups)
+      const int gtiles = ((int)s->nx + GT - 1) / GT * (((int)s->ny + GT - 1) / GT);
+      const int zc = (int)std::max<int64_t>(4, std::min<int64_t>(16, (int64_t)gtiles * s->nz / 2048));
+      const int gblocks = gtiles * (int)((s->nz + zc - 1) / zc);
+      auto gradient = [&](const double* u1, const double* u2, const double* wm) {
+        const bool tri = s->element == OVFEM_ELEMENT_TRILINEAR;
+        if (u2 && tri)
+          ovfem_gradient_kernel<1, true><<<gblocks, GT * GT, 0, s->stream>>>(g, zc, s->h, s->mat.p, u1, u2, bd, wm,
+                                                                             g_lam, g_mu);
+        else if (u2)
+          ovfem_gradient_kernel<0, true><<<gblocks, GT * GT, 0, s->stream>>>(g, zc, s->h, s->mat.p, u1, u2, bd, wm,
+                                                                             g_lam, g_mu);
+        else if (tri)
+          ovfem_gradient_kernel<1, false><<<gblocks, GT * GT, 0, s->stream>>>(g, zc, s->h, s->mat.p, u1, nullptr, bd,
+                                                                              wm, g_lam, g_mu);
+        else
+          ovfem_gradient_kernel<0, false><<<gblocks, GT * GT, 0, s->stream>>>(g, zc, s->h, s->mat.p, u1, nullptr, bd,
+                                                                              wm, g_lam, g_mu);
+        OVFEM_HIP(hipGetLastError());
+      };
 
       for (int64_t sg = (n - 1) / every; sg >= 0; --sg) {
         const int64_t s0 = sg * every, e0 = std::min(s0 + every, n);
@@ -1523,15 +1545,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           launch_unit<MODE_STEP>(s->form(), B, nullptr, m - 1, s->stream);
           i2 = i1;
           i1 = inew;
-          const double* u1 = state(m - 1 - s0);
-          const double* u2 = damped ? state(m - 2 - s0) : nullptr;
-          if (s->element == OVFEM_ELEMENT_TRILINEAR)
-            ovfem_gradient_kernel<1><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, u1, u2, bd, w[i1], g_lam,
-                                                                      g_mu);
-          else
-            ovfem_gradient_kernel<0><<<gblocks, NTHR, 0, s->stream>>>(g, s->h, s->mat.p, u1, u2, bd, w[i1], g_lam,
-                                                                      g_mu);
-          OVFEM_HIP(hipGetLastError());
+          gradient(state(m - 1 - s0), damped ? state(m - 2 - s0) : nullptr, w[i1]);
         }
       }
       OVFEM_HIP(hipStreamSynchronize(s->stream));
