@@ -524,6 +524,10 @@ def main():
                 states[p] = state  # also the start of the stage sweep and the trilinear timings
             print("[bench] full run of %d steps on %s: %.4f ms/step" % (full, p, sustained[p]), file=sys.stderr,
                   flush=True)
+        if state is not None:
+            # the same steps once untimed: the first steps from a restored state in a process
+            # ran 5-10 % slower than any later ones (measured on the 256 x 256 x 128 model)
+            time_run(runs[p], args.warmup, args.steps, state)
         ms = time_run(runs[p], args.warmup, args.steps, state)
         res[p] = {"ms_per_step": ms, "value": free_dof / (ms * 1e-3), "tuning": runs[p].tuning}
         if batched:
