@@ -141,6 +141,34 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
+def data_probe(paths):
+    """The stepper kernels on the 512 x 512 x 256 model from an all-zero wavefield and from a
+    uniform random one (the same instructions; the staging exponent is the same in every
+    layer of both), alternated twice, 30 steps each: ms per step from HIP events, for a
+    counter pass that reads the clock as GRBM_GUI_ACTIVE cycles over the kernel time."""
+    import torch
+
+    from paper_2404_13683_amd import workloads
+    from paper_2404_13683_amd.ovfem import Solver
+    w = workloads.topography_c5(nt=400)
+    n = 3 * w.n_nodes
+    zero = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    r1 = (torch.rand(n, dtype=torch.float64, device="cuda", generator=g) - 0.5) * 1e-6
+    r2 = (torch.rand(n, dtype=torch.float64, device="cuda", generator=g) - 0.5) * 1e-6
+    out = {}
+    for p in paths:
+        s = Solver.from_workload(w, precision=p, receivers_nt=w.nt + 1)
+        s.set_tuning(chunk_planes={"int8": 48, "fp64": 64}.get(p, 24))
+        out[p] = []
+        for name, (a, b) in (("zero", (zero, zero)), ("random", (r1, r2))) * 2:
+            s.set_wavefield(a, b)
+            out[p].append((name, _timed(s.step, 5, 25)))
+        s.close()
+    print(json.dumps({"data_probe_ms_per_step": out}))
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=10):
     """Bytes per second (read + written) of a plain device copy of nbytes: the bandwidth an
     HBM-bound kernel can reach on this GPU in practice."""
@@ -478,12 +506,19 @@ def main():
     ap.add_argument("--stage-sweep", action="store_true",
                     help="also time the INT8 path with 4..7 digit stages (accuracy/speed trade, Table 3)")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many bytes")
+    ap.add_argument("--data-probe", action="store_true",
+                    help="only time the stepper kernels (--paths) on a zero and on a random wavefield")
     ap.add_argument("--ckpt-every", type=int, default=0,
                     help="c4-adjoint: checkpoint interval (default: 1, every state on a tape in HBM and no "
                          "recompute, when it takes at most half the free memory; else 50)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.data_probe:
+        import torch
+        torch.cuda.set_device(0)
+        data_probe(args.paths.split(","))
         return
     if args.gpus != 1:
         print("bench.py: the stepper runs on one GPU (--gpus %d requested); it does not shard a "
