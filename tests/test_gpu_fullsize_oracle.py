@@ -2,8 +2,9 @@
 
 The references were written by tests/golden/make_fullsize_oracle.py, which steps the FP64
 oracle over the whole run on the host (tens of minutes per case):
-  * two shots of the 64-shot 128 x 128 x 64 workload, 1000 steps: receiver traces at every
+  * four shots of the 64-shot 128 x 128 x 64 workload, 1000 steps: receiver traces at every
     10th step, against all 64 shots advanced in one launch per step on each path;
+  * the layered 256 x 256 x 128 workload, 2000 steps: receiver traces at every 20th step;
   * the 96^3 adjoint workload, 1000 steps, checkpoints every 50: the misfit J and the
     discrete-adjoint gradient at 50 seeded voxels, against the GPU adjoint on each path.
 Targets: 1e-9 relative on traces and gradients (relative L2 over the stored samples).
@@ -41,7 +42,7 @@ def _c3_fixtures():
 def test_c3_shots_against_full_length_oracle_runs():
     from paper_2404_13683_amd.ovfem import Solver
     fixtures = _c3_fixtures()
-    assert len(fixtures) >= 2
+    assert len(fixtures) >= 4
     w = wl.shots_c3()
     for shot, fx in fixtures:
         assert fx["nt"] == w.nt and fx["rec_node"] == [int(r) for r in w.rec_node]
@@ -56,6 +57,28 @@ def test_c3_shots_against_full_length_oracle_runs():
             err = _rel(tr[shot][..., fx["steps"]], np.array(fx["traces"]))
             print("c3 shot %d %s vs the oracle over %d steps: rel L2 %.3e" % (shot, prec, w.nt, err))
             assert err <= TOL
+
+
+@pytest.mark.timeout(600)
+def test_c2_against_the_full_length_oracle_run():
+    """The layered 256 x 256 x 128 model over its whole 2000 steps on every path, against the
+    oracle's own 2000-step run (receiver traces at every 20th step)."""
+    from paper_2404_13683_amd.ovfem import Solver
+    fx = json.load(open(os.path.join(GOLDEN, "fullsize_c2.json")))
+    w = wl.layered_c2()
+    assert fx["nt"] == w.nt and fx["rec_node"] == [int(r) for r in w.rec_node]
+    assert (fx["nx"], fx["ny"], fx["nz"]) == (w.nx, w.ny, w.nz) and fx["dt"] == w.dt
+    ref = np.array(fx["traces"])
+    for prec in PATHS:
+        s = Solver.from_workload(w, precision=prec)
+        s.autotune(steps=4)
+        s.reset()
+        s.step(w.nt)
+        tr = s.get_traces().cpu().numpy()[0]
+        s.close()
+        err = _rel(tr[..., fx["steps"]], ref)
+        print("c2 %s vs the oracle over %d steps: rel L2 %.3e" % (prec, w.nt, err))
+        assert err <= TOL
 
 
 @pytest.mark.timeout(900)
