@@ -533,6 +533,8 @@ def main():
     full = FULL_STEPS[args.workload]
     if args.steps is None:
         args.steps = full
+    if args.steps < 1 or args.warmup < 0:
+        raise SystemExit("bench.py: --steps must be at least 1 and --warmup at least 0")
 
     import torch
 
