@@ -104,6 +104,15 @@ def measured_traffic(workload, path_name):
     return (f + w) * 1024.0
 
 
+def traffic_config(workload, path_name):
+    """The launch configuration the committed counters were taken at (chunk depth; 16-row
+    tiles), so that `traffic` can be read beside the tuned configuration of the run."""
+    kv = _counter_values(workload)
+    if kv is None or "%s_chunk_planes" % path_name not in kv:
+        return None
+    return {"chunk_planes": int(float(kv["%s_chunk_planes" % path_name])), "tile_rows": 16}
+
+
 def profile_counters(workload, path_name):
     """Busy fractions of the stepper kernel from the committed counter summary."""
     kv = _counter_values(workload)
@@ -604,7 +613,8 @@ def main():
                    "domains": [[w.nx, w.ny, w.nz, w.n_shots] for w in wls] if len(wls) > 1 else
                    [wls[0].nx, wls[0].ny, wls[0].nz, wls[0].n_shots]},
         "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": hbm / HBM_PEAK, "traffic": measured_traffic(args.workload, head), "kernel_sha": sha,
+                     "frac": hbm / HBM_PEAK, "traffic": measured_traffic(args.workload, head),
+                     "traffic_config": traffic_config(args.workload, head), "kernel_sha": sha,
                      "algorithmic_bytes_per_launch": bytes_step,
                      "mfma_frac_int8_peak": (INT8_OPS_PER_ELEMENT * n_elem / (ms * 1e-3)) / INT8_PEAK
                      if head.startswith("int8") else None},
