@@ -27,10 +27,13 @@ struct Error : std::runtime_error {
   Error(ovfem_status c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// A failed HIP call also leaves its error as the runtime's last error, which the next
+// hipGetLastError() (after a later, good launch) would report again: it is consumed here.
 #define OVFEM_HIP(expr)                                                                       \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \
     if (e_ != hipSuccess) {                                                                   \
+      (void)hipGetLastError();                                                                \
       throw Error(e_ == hipErrorOutOfMemory ? OVFEM_ENOMEM : OVFEM_EDEVICE,                   \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                        \
     }                                                                                         \
@@ -1421,6 +1424,9 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
     if (every > 0) {
       slots = max_steps / every + 1;
       // every = 1: the tape u^{-1} .. u^{max_steps}; otherwise a (u^s, u^{s-1}) pair per slot
+      const double vectors = every == 1 ? (double)slots + 1.0 : 2.0 * (double)slots;
+      require(vectors * (double)s->vec() * sizeof(double) < 1e18,
+              "ovfem_set_checkpointing: max_steps / every too large for any device", OVFEM_ENOMEM);
       buf.alloc((size_t)(every == 1 ? slots + 1 : slots * 2) * s->vec());
     }
     OVFEM_HIP(hipStreamSynchronize(s->stream));

@@ -106,6 +106,29 @@ def test_checkpoint_tape_capacity(prec):
         x.close()
 
 
+def test_checkpoint_store_that_cannot_fit_is_refused_without_side_effects():
+    """A checkpoint store beyond any device (size overflow) or beyond this one (34 TB) is
+    refused with ENOMEM, and the solver keeps its state and its earlier checkpointing."""
+    import torch
+
+    from paper_2404_13683_amd.ovfem import OvfemError, Solver
+    w, d_obs = _case(seed=10)
+    _, a_lam, _ = _gpu_gradient(w, d_obs, "fp64", every=3)
+    s = Solver.from_workload(w, precision="fp64")
+    s.set_checkpointing(3, w.nt)
+    s.step(20)
+    for every, max_steps in ((1, 10 ** 15), (1, 10 ** 9)):
+        with pytest.raises(OvfemError) as err:
+            s.set_checkpointing(every, max_steps)
+        assert err.value.status == -2  # OVFEM_ENOMEM
+    assert s.get_step() == 20
+    s.step(w.nt - 20)
+    res = (s.get_traces() - torch.from_numpy(d_obs).cuda()[None]).contiguous()
+    g_lam, _ = s.adjoint(res)
+    assert np.array_equal(g_lam.cpu().numpy(), a_lam)
+    s.close()
+
+
 def test_gpu_adjoint_against_central_differences():
     """Adjoint workload recipe at reduced size: FD on seeded voxels with |g| >= 1e-2 max |g|."""
     import torch
