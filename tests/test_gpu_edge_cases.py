@@ -193,3 +193,19 @@ def test_binding_rejects_bad_tensors():
         with pytest.raises((TypeError, ValueError)):
             s.set_wavefield(t, good)
     assert torch.count_nonzero(s.matvec(good)) == 0
+
+
+def test_solver_that_does_not_fit_is_refused_and_the_next_one_runs():
+    """A grid whose wavefields cannot fit (64 shots of 2000 x 2000 x 500: about 6 TB) is
+    refused with ENOMEM, and a solver made afterwards steps and matches the oracle."""
+    from paper_2404_13683_amd.ovfem import OvfemError, Solver
+    with pytest.raises(OvfemError) as err:
+        Solver(2000, 2000, 500, 1.0, precision="int8", n_shots=64)
+    assert err.value.status == -2  # OVFEM_ENOMEM
+    w = _case(seed=61, nt=60)
+    m = _model(w)
+    ref, _, _, _ = oasm.simulate(m, w.nt, w.src_node, w.src_comp, w.wavelet, w.rec_node)
+    s = Solver.from_workload(w, precision="int8")
+    s.step(w.nt)
+    assert _rel(s.get_traces().cpu().numpy()[0], ref) <= TOL
+    s.close()
