@@ -124,7 +124,7 @@ def test_damped_shots_batch_resume_and_tuning_are_bitwise(prec):
     before = _state(s)
     s.autotune(steps=4)
     _same(_state(s), before)
-    s.set_tuning(chunk_planes=16)  # the tiling the reference ran with (INT8 digits follow the tiling)
+    s.set_tuning(chunk_planes=16, tile_rows=16)  # the tiling the reference ran with (INT8 digits follow it)
     s.step(w.nt - 25)
     got, want = _state(s), _state(ref)
     _same(got[:2], want[:2])

@@ -186,7 +186,7 @@ def test_c3_64_shots_128x128x64_1000_steps():
     u = s.get_wavefield(0).view(w.n_shots, -1).cpu().numpy()
     for k in (0, 41):
         one = Solver.from_workload(wl.single_shot(w, k), precision="int8")
-        one.set_tuning(chunk_planes=tuning["chunk_planes"])
+        one.set_tuning(chunk_planes=tuning["chunk_planes"], tile_rows=tuning["tile_rows"])
         one.step(w.nt)
         assert np.array_equal(one.get_traces().cpu().numpy()[0], tr[k]), k
         assert np.array_equal(one.get_wavefield(0).cpu().numpy(), u[k]), k
