@@ -172,12 +172,13 @@ ovfem_status ovfem_get_traces(ovfem_solver* s, double* out);
 ovfem_status ovfem_get_step(ovfem_solver* s, int64_t* step);
 
 /* Checkpointing of forward runs for ovfem_adjoint: allocates room for max_steps steps
- * and, from now on, stores (u^s, u^{s-1}) on the device at every step s that is a
- * multiple of `every` (counted from reset).  every = 0 disables it.  Resets the
- * wavefield (as ovfem_reset).  Device memory: 2 (max_steps / every + 1) nodal vectors;
- * with every = 1, max_steps + 2: the forward run then writes each new state straight
- * into its slot of one tape u^{-1}, u^0, ..., and the adjoint recomputes nothing.
- * EINVAL with every > 0 on a solver of more than one shot; ENOMEM if it does not fit. */
+ * and, from now on, stores (u^s, u^{s-1}) of every shot on the device at every step s
+ * that is a multiple of `every` (counted from reset).  every = 0 disables it.  Resets the
+ * wavefield (as ovfem_reset).  Device memory: 2 (max_steps / every + 1) nodal vectors
+ * per shot; with every = 1, max_steps + 2 per shot: the forward run then writes each new
+ * state straight into its slot of one tape u^{-1}, u^0, ..., and the adjoint recomputes
+ * nothing.  ENOMEM if it does not fit (the solver keeps its state and its earlier
+ * checkpointing). */
 ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max_steps);
 
 /* Gradient of a receiver misfit with respect to the per-element lam and mu, by the
@@ -193,9 +194,12 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
  * b = beta / dt.
  * Requires a forward run of N >= 1 steps from reset with checkpointing enabled, the same
  * precision, model and dt, and receivers recording every step (N <= nt_max).
- * residual: DEVICE float64 [receiver][component][nt_max] (the layout of the traces;
+ * residual: DEVICE float64 [shot][receiver][component][nt_max] (the layout of the traces;
  * entries t >= N are ignored), e.g. traces - observed for J = 1/2 |traces - observed|^2.
- * g_lam, g_mu: DEVICE float64 arrays of nx*ny*nz, overwritten (0 for removed voxels).
+ * g_lam, g_mu: DEVICE float64 arrays of nx*ny*nz, overwritten (0 for removed voxels):
+ * the gradient of a misfit summed over the shots, i.e. the shots' gradients summed (each
+ * element's terms added step by step, shot by shot within a step).  The adjoint states of
+ * all shots advance in one launch per step, as the forward steps do.
  * Each checkpoint segment is recomputed forward (bitwise identical: the kernels are
  * deterministic; every - 1 steps per segment, none with every = 1, which trades two
  * stored nodal vectors per step for the recompute) and then stepped backward; the

@@ -42,7 +42,7 @@ def traces(solver, lam, mu, rho, solid=None, nt=None, ckpt_every=50):
     lam, mu: CUDA float64 tensors shaped (nz, ny, nx); rho, solid: host arrays.  The
     solver's dt, fixed nodes, sources and receivers must be set (receivers recording
     at least nt steps).  Backward must run before the solver is used for another run.
-    ckpt_every = 1 keeps every state ((nt + 2) nodal vectors of device memory) and the
+    ckpt_every = 1 keeps every state ((nt + 2) nodal vectors per shot of device memory) and the
     backward then recomputes nothing; larger intervals trade recompute for memory.
     """
     nt = solver.rec_nt if nt is None else int(nt)

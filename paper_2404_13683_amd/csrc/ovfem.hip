@@ -385,8 +385,9 @@ struct ovfem_solver {
   // every > 1: pairs [slot][which]; every = 1: one tape of states u^{-1}, u^0, u^1, ...
   // that the forward run steps through directly (no copies)
   double* ckpt_u(int64_t slot, int which) {
-    if (ckpt_every == 1) return ckpt.p + (size_t)(slot + 1 - which) * vec();
-    return ckpt.p + (size_t)(2 * slot + which) * vec();
+    const size_t all = (size_t)n_shots * vec();  // every shot's nodal vector, [shot][node][3]
+    if (ckpt_every == 1) return ckpt.p + (size_t)(slot + 1 - which) * all;
+    return ckpt.p + (size_t)(2 * slot + which) * all;
   }
 
   void check_device() {
@@ -609,11 +610,12 @@ struct ovfem_solver {
       for (; done + graph_steps <= n; done += graph_steps) OVFEM_HIP(hipGraphLaunch(graph[phase], stream));
       step += done;  // an even count: the phase is unchanged
     }
-    if (ckpt_valid && ckpt_every == 1 && n_shots == 1) {
+    if (ckpt_valid && ckpt_every == 1) {
       // every state kept: step through the tape, u^{s+1} written straight to its slot
+      // (every shot in one launch, as launch_step does without a grid cap)
       const int64_t m = std::min<int64_t>(n - done, ckpt_slots - 1 - step);
       if (m > 0) {
-        const size_t bytes = vec() * sizeof(double);
+        const size_t bytes = (size_t)n_shots * vec() * sizeof(double);
         OVFEM_HIP(hipMemcpyAsync(ckpt_u(step, 0), u[buf_cur(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
         OVFEM_HIP(hipMemcpyAsync(ckpt_u(step, 1), u[buf_prev(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
         for (int64_t i = 0; i < m; ++i) {
@@ -621,7 +623,7 @@ struct ovfem_solver {
           A.u = ckpt_u(step, 0);
           A.uprev = ckpt_u(step, 1);
           A.unext = ckpt_u(step + 1, 0);
-          A.n_units = 1;
+          A.n_units = n_shots;
           A.unit_u = (long long)vec();
           A.unit_src = geom.n_wg + 1;
           A.unit_tr = (long long)n_rec * 3 * rec_nt;
@@ -638,7 +640,7 @@ struct ovfem_solver {
       if (ckpt_valid && step % ckpt_every == 0) {
         const int64_t slot = step / ckpt_every;
         if (slot < ckpt_slots) {
-          const size_t bytes = vec() * sizeof(double);
+          const size_t bytes = (size_t)n_shots * vec() * sizeof(double);
           OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 0), u[buf_cur(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
           OVFEM_HIP(hipMemcpyAsync(ckpt_u(slot, 1), u[buf_prev(phase)].p, bytes, hipMemcpyDeviceToDevice, stream));
         } else {
@@ -1417,7 +1419,6 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
   return guarded([&] {
     require(s != nullptr, "ovfem_set_checkpointing: solver is NULL");
     require(every >= 0 && max_steps >= 0, "ovfem_set_checkpointing: negative argument");
-    require(every == 0 || s->n_shots == 1, "ovfem_set_checkpointing: the adjoint needs a one-shot solver");
     s->check_device();
     DevBuf<double> buf;
     int64_t slots = 0;
@@ -1425,9 +1426,9 @@ ovfem_status ovfem_set_checkpointing(ovfem_solver* s, int64_t every, int64_t max
       slots = max_steps / every + 1;
       // every = 1: the tape u^{-1} .. u^{max_steps}; otherwise a (u^s, u^{s-1}) pair per slot
       const double vectors = every == 1 ? (double)slots + 1.0 : 2.0 * (double)slots;
-      require(vectors * (double)s->vec() * sizeof(double) < 1e18,
+      require(vectors * (double)s->n_shots * (double)s->vec() * sizeof(double) < 1e18,
               "ovfem_set_checkpointing: max_steps / every too large for any device", OVFEM_ENOMEM);
-      buf.alloc((size_t)(every == 1 ? slots + 1 : slots * 2) * s->vec());
+      buf.alloc((size_t)(every == 1 ? slots + 1 : slots * 2) * s->n_shots * s->vec());
     }
     OVFEM_HIP(hipStreamSynchronize(s->stream));
     std::swap(s->ckpt, buf);
@@ -1445,7 +1446,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
     require(residual && g_lam && g_mu, "ovfem_adjoint: NULL array");
     s->check_device();
     const int64_t n = s->step;
-    require(s->ckpt_valid && s->ckpt_every > 0 && s->n_shots == 1,
+    require(s->ckpt_valid && s->ckpt_every > 0,
             "ovfem_adjoint: the forward run since reset was not checkpointed (call ovfem_set_checkpointing, "
             "then step from reset without changing precision, tiling or wavefield)",
             OVFEM_ESTATE);
@@ -1454,21 +1455,28 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
     require(s->model_set && s->dt_set, "ovfem_adjoint: model and dt not set", OVFEM_ESTATE);
     s->refresh_acoef();
     const int64_t every = s->ckpt_every;
+    const int shots = s->n_shots;
     const size_t vec = s->vec();
+    const size_t all = (size_t)shots * vec;  // the nodal vectors of every shot, [shot][node][3]
     const Geom& g = s->geom;
 
-    // adjoint sources: each receiver component, driven by its residual row
+    // adjoint sources: each receiver component of each shot, driven by its residual row
+    // (shot v's tile lists at v (n_wg + 1), as the forward source tables are laid out)
     std::vector<std::vector<int>> per(g.n_wg);
     for (int r = 0; r < s->n_rec; ++r) per[ovfem_solver::tile_of(g, s->rec_node_h[r])].push_back(r);
-    std::vector<int> aptr(g.n_wg + 1, 0), anode, acomp, arow;
-    for (int w = 0; w < g.n_wg; ++w) {
-      for (int r : per[w])
-        for (int c = 0; c < 3; ++c) {
-          anode.push_back((int)s->rec_node_h[r]);
-          acomp.push_back(c);
-          arow.push_back(3 * r + c);
-        }
-      aptr[w + 1] = (int)anode.size();
+    std::vector<int> aptr((size_t)shots * (g.n_wg + 1), 0), anode, acomp, arow;
+    for (int v = 0; v < shots; ++v) {
+      int* ptr = aptr.data() + (size_t)v * (g.n_wg + 1);
+      ptr[0] = (int)anode.size();
+      for (int w = 0; w < g.n_wg; ++w) {
+        for (int r : per[w])
+          for (int c = 0; c < 3; ++c) {
+            anode.push_back((int)s->rec_node_h[r]);
+            acomp.push_back(c);
+            arow.push_back(3 * (v * s->n_rec + r) + c);
+          }
+        ptr[w + 1] = (int)anode.size();
+      }
     }
     DevBuf<int> d_aptr, d_anode, d_acomp, d_arow;
     DevBuf<double> seg, wbuf;
@@ -1482,20 +1490,25 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       upload(d_anode, anode, s->stream);
       upload(d_acomp, acomp, s->stream);
       upload(d_arow, arow, s->stream);
-      seg.alloc((size_t)(every + 1) * vec);
+      seg.alloc((size_t)(every + 1) * all);
       const bool damped = s->damped();
       const double bd = damped ? s->damp_b() : 0.0;
-      wbuf.alloc(3 * vec);
+      wbuf.alloc(3 * all);
       OVFEM_HIP(hipMemsetAsync(g_lam, 0, s->n_elem * sizeof(double), s->stream));
       OVFEM_HIP(hipMemsetAsync(g_mu, 0, s->n_elem * sizeof(double), s->stream));
-      OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 3 * vec * sizeof(double), s->stream));
+      OVFEM_HIP(hipMemsetAsync(wbuf.p, 0, 3 * all * sizeof(double), s->stream));
       // w[i1] = w^{m+1}, w[i2] = w^{m+2}; a step writes w^m over w^{m+2} (undamped) or
       // into the third buffer (damped: the halo of w^{m+2} is read by neighbours)
-      double* w[3] = {wbuf.p, wbuf.p + vec, wbuf.p + 2 * vec};
+      double* w[3] = {wbuf.p, wbuf.p + all, wbuf.p + 2 * all};
       int i1 = 0, i2 = 1;
 
-      KArgs F = s->shot_args(0, s->phase);  // forward recompute: forward sources, no recording
+      // forward recompute: forward sources, no recording; every shot in one launch
+      KArgs F = s->shot_args(0, s->phase);
       F.rec_nt = 0;
+      F.n_units = shots;
+      F.unit_u = (long long)vec;
+      F.unit_src = g.n_wg + 1;
+      F.unit_tr = 0;
       KArgs B = F;  // adjoint steps: the residual injected at the receivers
       B.src_ptr = d_aptr.p;
       B.src_node = d_anode.p;
@@ -1509,6 +1522,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
       const int gtiles = ((int)s->nx + GT - 1) / GT * (((int)s->ny + GT - 1) / GT);
       const int zc = (int)std::max<int64_t>(4, std::min<int64_t>(16, (int64_t)gtiles * s->nz / 2048));
       const int gblocks = gtiles * (int)((s->nz + zc - 1) / zc);
+      // one launch per shot, in shot order: each element's sums run over the shots in turn
       auto gradient = [&](const double* u1, const double* u2, const double* wm) {
         const bool tri = s->element == OVFEM_ELEMENT_TRILINEAR;
         if (u2 && tri)
@@ -1535,7 +1549,7 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
         auto state = [&](int64_t k) -> double* {
           if (k < 0) return s->ckpt_u(sg, 1);
           if (k == 0) return s->ckpt_u(sg, 0);
-          return seg.p + (size_t)k * vec;
+          return seg.p + (size_t)k * all;
         };
         for (int64_t t = s0; t + 1 < e0; ++t) {
           F.u = state(t - s0);
@@ -1551,7 +1565,9 @@ ovfem_status ovfem_adjoint(ovfem_solver* s, const double* residual, double* g_la
           launch_unit<MODE_STEP>(s->form(), B, nullptr, m - 1, s->stream);
           i2 = i1;
           i1 = inew;
-          gradient(state(m - 1 - s0), damped ? state(m - 2 - s0) : nullptr, w[i1]);
+          for (int v = 0; v < shots; ++v)
+            gradient(state(m - 1 - s0) + v * vec, damped ? state(m - 2 - s0) + v * vec : nullptr,
+                     w[i1] + v * vec);
         }
       }
       OVFEM_HIP(hipStreamSynchronize(s->stream));

@@ -295,7 +295,9 @@ class Solver:
         _check(_LIB.ovfem_set_checkpointing(self._h, int(every), int(max_steps)))
 
     def adjoint(self, residual):
-        """(g_lam, g_mu) as CUDA float64 tensors (nz, ny, nx) for dJ/d(traces) = residual."""
+        """(g_lam, g_mu) as CUDA float64 tensors (nz, ny, nx) for dJ/d(traces) = residual
+        ([shot][receiver][3][nt], the traces' layout); with several shots, the gradient of
+        a misfit summed over them."""
         import torch
         n = self.n_shots * self.n_rec * 3 * self.rec_nt
         r = residual.reshape(-1)

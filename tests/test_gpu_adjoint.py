@@ -129,6 +129,115 @@ def test_checkpoint_store_that_cannot_fit_is_refused_without_side_effects():
     s.close()
 
 
+def _shots_case(seed, n_shots=3, alpha=0.0, beta=0.0):
+    """The adjoint case with n_shots shots from different source points (shot 1 with two
+    sources), the same receivers; observations per shot from the oracle on a perturbed
+    model.  The misfit is summed over the shots, so its gradient is the sum of the shots'."""
+    w1, _ = _case(seed=seed)
+    nx, ny, nz, nt, dt = w1.nx, w1.ny, w1.nz, w1.nt, w1.dt
+    pts = [(nx // 2, ny // 2, nz, 2), (nx - 4, 3, nz, 0), (4, ny - 3, nz - 3, 1), (3, 3, nz, 2)][:n_shots + 1]
+    src = np.array([wl.node_id(i, j, k, nx, ny) for i, j, k, _ in pts], np.int64)
+    comp = np.array([c for *_, c in pts], np.int32)
+    shot = np.array([0, 1, 1, 2][:n_shots + 1], np.int32)
+    f0 = 1.0 / (18 * dt)
+    wav = np.stack([wl.ricker(nt, dt, f0 * (1.0 + 0.15 * v)) for v in range(len(pts))])
+    w = wl.Workload("adjoint-shots", nx, ny, nz, w1.h, w1.lam, w1.mu, w1.rho, w1.fixed, dt, nt, src, comp, shot,
+                    wav, w1.rec_node, n_shots=n_shots)
+    rng = np.random.default_rng(seed + 100)
+    mt = oasm.Model(w.lam * (1 + 0.1 * rng.standard_normal(w.lam.shape)),
+                    w.mu * (1 + 0.1 * rng.standard_normal(w.mu.shape)), w.rho, w.h, w.fixed, dt, alpha=alpha, beta=beta)
+    d_obs = np.stack([oasm.simulate(mt, nt, src[shot == v], comp[shot == v], wav[shot == v], w.rec_node)[0]
+                      for v in range(n_shots)])
+    return w, d_obs
+
+
+def _shot_solver(w, prec, alpha=0.0, beta=0.0):
+    from paper_2404_13683_amd.ovfem import Solver
+    s = Solver(w.nx, w.ny, w.nz, w.h, precision=prec, n_shots=w.n_shots)
+    s.set_model(w.lam, w.mu, w.rho, w.solid)
+    s.set_fixed_nodes(w.fixed)
+    if alpha or beta:
+        s.set_damping(alpha, beta)
+    s.set_dt(w.dt)
+    s.set_sources(w.src_node, w.src_comp, w.wavelet, w.src_shot)
+    s.set_receivers(w.rec_node, w.nt)
+    return s
+
+
+def _shots_gradient(w, d_obs, prec, every, alpha=0.0, beta=0.0, calls=(None,), **tuning):
+    import torch
+    s = _shot_solver(w, prec, alpha, beta)
+    if tuning:
+        s.set_tuning(**tuning)
+    s.set_checkpointing(every, w.nt)
+    left = w.nt
+    for n in calls:
+        n = left if n is None else n
+        s.step(n)
+        left -= n
+    tr = s.get_traces()
+    res = (tr - torch.from_numpy(d_obs).cuda()).contiguous()
+    g_lam, g_mu = (g.cpu().numpy() for g in s.adjoint(res))
+    u0 = s.get_wavefield(0).cpu().numpy()
+    assert s.get_step() == w.nt
+    s.close()
+    return tr.cpu().numpy(), g_lam, g_mu, u0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "int8", "fp64-sf"])
+def test_multi_shot_adjoint_sums_the_shots(prec):
+    """One solver of three shots: its gradient is the oracle's gradient summed over the
+    shots (1e-9), and the sum of one-shot solvers' GPU gradients to rounding (1e-12: the
+    shots' terms are added in another order); checkpoint segments of 7 steps, the tape
+    (every step kept, in uneven calls) and a capped grid give the same gradient bitwise."""
+    w, d_obs = _shots_case(seed=21)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    gl_ref = np.zeros_like(w.lam)
+    gm_ref = np.zeros_like(w.mu)
+    singles_l, singles_m = np.zeros_like(w.lam), np.zeros_like(w.mu)
+    for v in range(w.n_shots):
+        k = w.src_shot == v
+        _, gl, gm = oasm.adjoint_gradient(m, w.nt, w.src_node[k], w.src_comp[k], w.wavelet[k], w.rec_node, d_obs[v])
+        gl_ref += gl
+        gm_ref += gm
+        _, sl, sm = _gpu_gradient(wl.single_shot(w, v), d_obs[v], prec, every=7)
+        singles_l += sl
+        singles_m += sm
+    tr, g_lam, g_mu, u0 = _shots_gradient(w, d_obs, prec, every=7)
+    el, em = _rel(g_lam, gl_ref), _rel(g_mu, gm_ref)
+    print("three-shot adjoint %s: vs oracle %.3e %.3e, vs one-shot solvers %.3e %.3e"
+          % (prec, el, em, _rel(g_lam, singles_l), _rel(g_mu, singles_m)))
+    assert el <= 1e-9 and em <= 1e-9
+    assert _rel(g_lam, singles_l) <= 1e-12 and _rel(g_mu, singles_m) <= 1e-12
+    for every, calls, tuning in ((1, (13, 0, None), {}), (1, (None,), dict(persistent_groups=8)),
+                                 (60, (None,), dict(persistent_groups=8))):
+        tr2, l2, m2, u2 = _shots_gradient(w, d_obs, prec, every, calls=calls, **tuning)
+        assert np.array_equal(tr2, tr) and np.array_equal(u2, u0), (every, tuning)
+        assert np.array_equal(l2, g_lam) and np.array_equal(m2, g_mu), (every, tuning)
+
+
+def test_multi_shot_damped_adjoint():
+    """The damped recursion's adjoint over two shots against the oracle's, summed (1e-9),
+    with segments of 9 steps and with the tape (bitwise the same)."""
+    w0, _ = _case(seed=22)
+    f0 = 1.0 / (18 * w0.dt)
+    alpha, beta = oasm.rayleigh_coefficients(0.05, 0.8 * f0, 1.25 * f0)
+    w, d_obs = _shots_case(seed=22, n_shots=2, alpha=alpha, beta=beta)
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt, alpha=alpha, beta=beta)
+    gl_ref = np.zeros_like(w.lam)
+    gm_ref = np.zeros_like(w.mu)
+    for v in range(w.n_shots):
+        k = w.src_shot == v
+        _, gl, gm = oasm.adjoint_gradient(m, w.nt, w.src_node[k], w.src_comp[k], w.wavelet[k], w.rec_node, d_obs[v])
+        gl_ref += gl
+        gm_ref += gm
+    _, g_lam, g_mu, _ = _shots_gradient(w, d_obs, "int8", 9, alpha, beta)
+    print("two-shot damped adjoint: %.3e %.3e" % (_rel(g_lam, gl_ref), _rel(g_mu, gm_ref)))
+    assert _rel(g_lam, gl_ref) <= 1e-9 and _rel(g_mu, gm_ref) <= 1e-9
+    _, l1, m1, _ = _shots_gradient(w, d_obs, "int8", 1, alpha, beta, calls=(20, None))
+    assert np.array_equal(l1, g_lam) and np.array_equal(m1, g_mu)
+
+
 def test_gpu_adjoint_against_central_differences():
     """Adjoint workload recipe at reduced size: FD on seeded voxels with |g| >= 1e-2 max |g|."""
     import torch

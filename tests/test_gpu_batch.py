@@ -280,9 +280,6 @@ def test_tuning_rejects_bad_values():
     for bad in (dict(chunk_planes=0), dict(graph_steps=7), dict(graph_steps=-2), dict(persistent_groups=-1)):
         with pytest.raises(OvfemError):
             s.set_tuning(**bad)
-    multi = _solver(_small_shots(2, 10), "fp64")
-    with pytest.raises(OvfemError):
-        multi.set_checkpointing(5, 10)  # the adjoint takes one shot per solver
 
 
 @pytest.mark.parametrize("prec", PRECS)
