@@ -300,6 +300,43 @@ def test_autograd_function_gives_the_adjoint_gradient():
     assert _rel(mu.grad.cpu().numpy(), gm_ref) <= 1e-9
 
 
+def test_autograd_over_several_shots():
+    """torch.autograd through a two-shot solver, with a misfit that weighs the shots
+    differently: the gradient is the library's adjoint of that residual (bitwise) and the
+    oracle's weighted sum of the shots' gradients (1e-9)."""
+    import torch
+
+    from paper_2404_13683_amd import autograd
+    w, d_obs = _shots_case(seed=23, n_shots=2)
+    s = _shot_solver(w, "int8")
+    lam = torch.from_numpy(w.lam).cuda().requires_grad_(True)
+    mu = torch.from_numpy(w.mu).cuda().requires_grad_(True)
+    tr = autograd.traces(s, lam, mu, w.rho, nt=w.nt, ckpt_every=1)
+    obs = torch.from_numpy(d_obs).cuda()
+    J = 0.5 * ((tr[0] - obs[0]) ** 2).sum() + 1.5 * ((tr[1] - obs[1]) ** 2).sum()
+    J.backward()
+    weight = np.array([1.0, 3.0])[:, None, None, None]
+    _, g_lam, g_mu, _ = _shots_gradient(w, d_obs, "int8", 1)  # residual weights 1, 1
+    m = oasm.Model(w.lam, w.mu, w.rho, w.h, w.fixed, w.dt)
+    gl_ref, gm_ref = np.zeros_like(w.lam), np.zeros_like(w.mu)
+    for v in range(2):
+        k = w.src_shot == v
+        _, gl, gm = oasm.adjoint_gradient(m, w.nt, w.src_node[k], w.src_comp[k], w.wavelet[k], w.rec_node, d_obs[v])
+        gl_ref += weight[v, 0, 0, 0] * gl
+        gm_ref += weight[v, 0, 0, 0] * gm
+    assert _rel(lam.grad.cpu().numpy(), gl_ref) <= 1e-9 and _rel(mu.grad.cpu().numpy(), gm_ref) <= 1e-9
+    # the same residual handed to the library directly
+    s2 = _shot_solver(w, "int8")
+    s2.set_checkpointing(1, w.nt)
+    s2.step(w.nt)
+    res = (torch.from_numpy(weight).cuda() * (s2.get_traces() - obs)).contiguous()
+    d_lam, d_mu = s2.adjoint(res)
+    assert torch.equal(d_lam, lam.grad) and torch.equal(d_mu, mu.grad)
+    assert not np.array_equal(d_lam.cpu().numpy(), g_lam)  # the weights matter
+    s.close()
+    s2.close()
+
+
 def test_autograd_backward_refuses_a_solver_used_for_another_run():
     import torch
 
