@@ -343,6 +343,21 @@ def single_shot(w, shot):
                                wavelet=w.wavelet[sel], n_shots=1)
 
 
+def with_surface_shots(w, n, seed=0):
+    """w with n shots: shot 0 is w's one-shot source set, shots 1 .. n-1 the same first
+    source (component, wavelet) moved to seeded top-surface nodes away from the receivers."""
+    import dataclasses
+    assert w.n_shots == 1
+    rng = np.random.default_rng(seed)
+    extra = surface_nodes(rng, n - 1, w.nx, w.ny, w.nz, exclude=np.concatenate([w.src_node, w.rec_node]))
+    return dataclasses.replace(
+        w, name="%s-%dshots" % (w.name, n), n_shots=n,
+        src_node=np.concatenate([w.src_node, extra]),
+        src_comp=np.concatenate([w.src_comp, np.full(n - 1, w.src_comp[0], np.int32)]),
+        src_shot=np.concatenate([np.asarray(w.src_shot, np.int32), np.arange(1, n, dtype=np.int32)]),
+        wavelet=np.concatenate([w.wavelet, np.repeat(w.wavelet[:1], n - 1, axis=0)]))
+
+
 def random_field(shape, seed, scale=1.0):
     """Seeded standard-normal nodal field (for per-matvec parity)."""
     return scale * np.random.default_rng(seed).standard_normal(shape)

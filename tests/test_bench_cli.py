@@ -44,3 +44,25 @@ def test_algorithmic_bytes_count_free_nodes_and_solid_voxels():
     free = int(np.count_nonzero(touched & ~fixed))
     assert w.free_dof() == 3 * free
     assert bench.algorithmic_bytes(w) == 72 * free * w.n_shots + 8 * free + 16 * int(np.count_nonzero(solid))
+
+
+def test_adjoint_shot_count_below_one_is_refused():
+    r = _run("--workload", "c4-adjoint", "--adjoint-shots", "0")
+    assert r.returncode != 0
+    assert "--adjoint-shots must be at least 1" in (r.stderr + r.stdout)
+
+
+def test_surface_shots_keep_shot_zero_and_move_the_source():
+    """with_surface_shots: shot 0 is the workload's own source; the others are the same
+    component and wavelet at distinct top-surface nodes that are not receivers."""
+    sys.path.insert(0, ROOT)
+    from paper_2404_13683_amd import workloads as wl
+    _, w = wl.adjoint_c4(nx=12, ny=10, nz=8, nt=20, n_rec=6)
+    m = wl.with_surface_shots(w, 4, seed=3)
+    assert m.n_shots == 4 and list(m.src_shot) == [0, 1, 2, 3]
+    assert m.src_node[0] == w.src_node[0] and np.array_equal(m.wavelet[0], w.wavelet[0])
+    assert len(set(m.src_node.tolist())) == 4 and not set(m.src_node.tolist()) & set(w.rec_node.tolist())
+    k = m.src_node[1:] // ((w.nx + 1) * (w.ny + 1))
+    assert np.all(k == w.nz) and np.all(m.src_comp == w.src_comp[0])
+    assert all(np.array_equal(m.wavelet[v], w.wavelet[0]) for v in range(4))
+    assert np.array_equal(wl.single_shot(m, 0).src_node, w.src_node)
