@@ -347,7 +347,8 @@ def with_surface_shots(w, n, seed=0):
     """w with n shots: shot 0 is w's one-shot source set, shots 1 .. n-1 the same first
     source (component, wavelet) moved to seeded top-surface nodes away from the receivers."""
     import dataclasses
-    assert w.n_shots == 1
+    if w.n_shots != 1 or n < 1:
+        raise ValueError("with_surface_shots: needs a one-shot workload and n >= 1")
     rng = np.random.default_rng(seed)
     extra = surface_nodes(rng, n - 1, w.nx, w.ny, w.nz, exclude=np.concatenate([w.src_node, w.rec_node]))
     return dataclasses.replace(
